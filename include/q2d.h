@@ -1,0 +1,179 @@
+/*
+ * q2d.h -- C ABI of the quasi-2D long-range electrostatics library.
+ *
+ * The library evaluates, on one AMD MI355X (gfx950) GPU, the long-range part
+ * of the Ewald2D sum for N point charges in a box [0,Lx] x [0,Ly] x [0,Lz]
+ * that is periodic in x and y and confined in z (Sec. 2.1 of arXiv:2403.01521,
+ * the Poisson problem with doubly periodic boundary conditions).  The Fourier
+ * modes use the sum-of-exponentials (SOE) form of the kernels xi^+ + xi^-
+ * (Sec. 3.1), which makes every mode an O(N) pair of z-ordered prefix scans
+ * (Sec. 3.2, the recursion built on the z-sort); the random-batch entry point
+ * samples P modes by importance sampling (Sec. 4.1, Alg. 2).
+ *
+ * Conventions shared by every entry point:
+ *  - Units: Gaussian units, pair energy q_i q_j / r, force F_i = -grad_i U.
+ *  - Arrays: pos is N x 3 row-major (x0 y0 z0 x1 ...), q, phi have N entries,
+ *    F is N x 3 row-major.  The element type of pos, q, phi and F is double for
+ *    a Q2D_FP64 plan and float for a Q2D_FP32 plan.  E is always one double.
+ *  - Memory: every data pointer is a DEVICE pointer on the plan's device
+ *    (hipMalloc / torch CUDA tensors).  The caller owns all of them; the plan
+ *    owns only its internal scratch, sized at creation from n_max and p_max.
+ *  - Streams: work is enqueued asynchronously on the plan's HIP stream; outputs
+ *    are valid once that stream has reached the enqueued work.  One plan must
+ *    not be used from two host threads at once.
+ *  - Positions: x and y are wrapped into [0, L) (periodic); z is used as given
+ *    and must lie in [0, Lz] (confinement).  The system must be charge neutral
+ *    (Thm 2.1).  These two data conditions are checked on the device only when
+ *    opts.validate is set; the result is reported by q2d_plan_check.
+ *  - Outputs are overwritten, not accumulated.  NULL output pointers are
+ *    skipped.  N = 0 is valid and writes E = 0.
+ *  - Errors: every function returns a q2d_status; none throws or aborts.
+ */
+#ifndef Q2D_H
+#define Q2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct q2d_plan *q2d_plan_t;
+
+typedef enum {
+    Q2D_OK = 0,
+    Q2D_EINVAL = 1,        /* bad argument (null pointer, non-positive size, bad SOE table) */
+    Q2D_ENONNEUTRAL = 2,   /* |sum q| > 1e-6 sum |q| (Thm 2.1); reported by q2d_plan_check */
+    Q2D_EOUTOFBOX = 3,     /* z outside [0, Lz] or a non-finite input; by q2d_plan_check */
+    Q2D_ENOMEM = 4,        /* a device or host allocation failed */
+    Q2D_ECAPACITY = 5,     /* N > n_max or P > p_max */
+    Q2D_EDEVICE = 6,       /* a HIP runtime call failed */
+    Q2D_ESAMPLER = 7,      /* the mode sampler found no non-zero proposal */
+    Q2D_EUNSUPPORTED = 8   /* the plan was created without what this call needs */
+} q2d_status;
+
+typedef enum { Q2D_FP64 = 0, Q2D_FP32 = 1 } q2d_precision;
+
+typedef struct {
+    int32_t precision;  /* q2d_precision: element type of pos, q, phi, F and of the scans */
+    int32_t thin;       /* Metropolis thinning D >= 1 (App. G); 0 means 1 */
+    int64_t n_max;      /* largest N any call on this plan will pass (> 0) */
+    int32_t p_max;      /* largest batch size P of q2d_rbm_step (0: random batch unused) */
+    int32_t validate;   /* nonzero: check neutrality, z in [0, Lz], finiteness on the device */
+} q2d_opts;
+
+/* Read-only facts about a plan (host values). */
+typedef struct {
+    int64_t n_modes_exact;  /* modes 0 < |k| <= k_c on the half lattice used by q2d_long_range */
+    int32_t M;              /* number of SOE terms */
+    double H;               /* sum_{k != 0} exp(-k^2 / (4 alpha^2)) (Sec. 4.1, eq. hk) */
+    double diag_exact;      /* (pi/A) sum_{0<|k|<=k_c} e^{-k^2/4a^2} K_k(0): j = i constant, exact-k */
+    double diag_rb;         /* the same sum over every k != 0: j = i constant, random batch */
+    double soe_k0_self;     /* K_0(0) = sum_l w_l / (alpha sqrt(pi)) (eq. 32 at z = 0) */
+} q2d_info;
+
+/*
+ * q2d_plan_create -- set up a solver for one box and one SOE table.
+ *
+ * Lx, Ly, Lz > 0: box (Sec. 2.1).  alpha > 0: Ewald splitting parameter
+ * (Sec. 2.2).  r_c: real-space cutoff for q2d_short_range (<= 0 disables it;
+ * otherwise 0 < r_c <= min(Lx, Ly) / 2).  k_c: Fourier cutoff of
+ * q2d_long_range (<= 0 disables that entry point).  M, w, s: the SOE
+ * exp(-x^2) ~ sum_l w_l exp(-s_l |x|) (Sec. 3, eq. SOE1; the plan uses
+ * beta_l = alpha s_l); w and s are HOST arrays of 2M doubles, (re, im)
+ * interleaved.  The table must be closed under complex conjugation, have
+ * Re s_l > 0 and no real node (Im s_l = 0), so that beta_l^2 != k^2 for every
+ * real k; otherwise Q2D_EINVAL.  opts: see q2d_opts (NULL: FP64, n_max = 0 is
+ * invalid, so opts is required).  stream: a hipStream_t (NULL = default
+ * stream).  On success *out holds a new plan.  The plan binds the device that
+ * is current at creation.
+ */
+q2d_status q2d_plan_create(double Lx, double Ly, double Lz, double alpha, double r_c, double k_c,
+                           int32_t M, const double *w, const double *s, const q2d_opts *opts,
+                           void *stream, q2d_plan_t *out);
+
+/* Release a plan and its device scratch (synchronises the plan's stream first). */
+q2d_status q2d_plan_destroy(q2d_plan_t plan);
+
+/* Bind later calls to another hipStream_t. */
+q2d_status q2d_plan_set_stream(q2d_plan_t plan, void *stream);
+
+/* Copy the plan's host-side facts into *info. */
+q2d_status q2d_plan_info(q2d_plan_t plan, q2d_info *info);
+
+/*
+ * q2d_long_range -- SOEwald2D long-range sum over all 0 < |k| <= k_c
+ * (Alg. 1, Fourier part; Sec. 3.2 recursion; forces of App. E).
+ *
+ * Writes phi_i = sum_{0<|k|<=k_c} phi^k_SOE(r_i) + phi^0_SOE(r_i) - phi_self^i,
+ * where both Fourier parts include the j = i term (Sec. 2.2: phi_l contains
+ * the Gaussian cloud's action on its own charge, phi_self = 2 alpha q_i/sqrt(pi)
+ * removes it), F_i = -grad_i U_l, and E = 1/2 sum_i q_i phi_i (FP64).
+ * pos, q: device inputs (N x 3, N); phi (N), F (N x 3), E (1 double): device
+ * outputs or NULL.  Q2D_EUNSUPPORTED if the plan has k_c <= 0.
+ */
+q2d_status q2d_long_range(q2d_plan_t plan, const void *pos, const void *q, int64_t N, void *phi,
+                          void *F, double *E);
+
+/*
+ * q2d_rbm_step -- random-batch SOE long-range sum (RBSE2D, Alg. 2, Fourier part).
+ *
+ * Draws P modes k_eta != 0 from h(k) = exp(-k^2/(4 alpha^2)) / H over the whole
+ * lattice with the Metropolis chain of App. G driven by Philox4x32-10 with
+ * key = seed and counter = (draw, step, stream); the same (seed, step) gives
+ * the same modes.  Writes the estimator (eq. RBapp) of the k != 0 part for
+ * every pair j != i, weight (pi/A) H/P per sampled mode, plus the deterministic
+ * j = i constant q_i * diag_rb, plus the exact (SOE) k = 0 term and minus
+ * phi_self, with forces and E as in q2d_long_range.  modes_out: device int32
+ * array of P x 2 (mx, my) with k = 2 pi (mx/Lx, my/Ly), or NULL.
+ * Q2D_ECAPACITY if P > p_max.
+ */
+q2d_status q2d_rbm_step(q2d_plan_t plan, const void *pos, const void *q, int64_t N, int32_t P,
+                        uint64_t seed, uint64_t step, void *phi, void *F, double *E,
+                        int32_t *modes_out);
+
+/*
+ * q2d_short_range -- real-space part phi_s (eq. phi_s) with cutoff r_c by a
+ * uniform cell list: phi_i = sum over images m and j (j != i when m = 0) with
+ * |r_ij + M| <= r_c of q_j erfc(alpha r)/r, the matching force and
+ * E = 1/2 sum q_i phi_i.  Q2D_EUNSUPPORTED if the plan has r_c <= 0.
+ */
+q2d_status q2d_short_range(q2d_plan_t plan, const void *pos, const void *q, int64_t N, void *phi,
+                           void *F, double *E);
+
+/*
+ * q2d_plan_check -- wait for the plan's stream and return the first data error
+ * found by the device-side checks of the calls since the last check
+ * (Q2D_ENONNEUTRAL, Q2D_EOUTOFBOX, Q2D_ESAMPLER) or Q2D_OK; clears it.
+ */
+q2d_status q2d_plan_check(q2d_plan_t plan);
+
+/*
+ * q2d_soe_fit -- host FP64 SOE of exp(-x^2) with M terms (M even, 2 <= M <= 64)
+ * by the midpoint rule on Weideman's optimised Talbot contour applied to the
+ * inverse-Laplace representation of the Gaussian (Sec. 3), with the contour
+ * scale that minimises the sup-norm error.  w, s: host arrays of 2M doubles
+ * (re, im interleaved) filled on success; *sup_err (may be NULL) receives
+ * max |exp(-x^2) - SOE(x)| measured on a grid of [0, 200].
+ */
+q2d_status q2d_soe_fit(int32_t M, double *w, double *s, double *sup_err);
+
+/*
+ * Kernel timing (measurement only): when enabled, the plan records HIP events
+ * around the launches of one kernel family on its stream and accumulates
+ * their elapsed time.  which: 0 = k != 0 sweep (the hot kernel), 1 = k != 0
+ * aggregate pass, 2 = z-sort, 3 = k = 0 term, 4 = whole call.
+ * q2d_plan_timing_read synchronises and returns total milliseconds and the
+ * number of launches measured since the last reset (enable resets).
+ */
+q2d_status q2d_plan_timing_enable(q2d_plan_t plan, int32_t enable);
+q2d_status q2d_plan_timing_read(q2d_plan_t plan, int32_t which, double *ms_total, int64_t *count);
+
+/* Static description of a status code. */
+const char *q2d_status_string(q2d_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* Q2D_H */

@@ -1,0 +1,233 @@
+"""Python binding of libq2d (the C ABI in include/q2d.h).
+
+Quasi-2D long-range electrostatics on an AMD MI355X: the SOE Ewald2D sum
+(arXiv:2403.01521, Sec. 3) and its random-batch form (Sec. 4).  This module
+only marshals arguments: every step of the computation runs in the HIP
+kernels of libq2d.so.  PyTorch supplies device memory and the stream.
+
+    import paper_2403_01521_amd as q2d
+    w, s, err = q2d.soe_fit(16)
+    plan = q2d.Plan(box=(600, 600, 10), alpha=0.1, w=w, s=s, precision="fp32",
+                    n_max=10**6, p_max=100)
+    phi, F, E, modes = plan.rbm_step(pos, q, P=100, seed=1, step=0)
+
+There is no CPU fallback: importing works without a GPU (for symbol checks),
+but every compute call needs the built library and a HIP device.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libq2d.so")
+
+STATUS = {
+    0: "Q2D_OK", 1: "Q2D_EINVAL", 2: "Q2D_ENONNEUTRAL", 3: "Q2D_EOUTOFBOX", 4: "Q2D_ENOMEM",
+    5: "Q2D_ECAPACITY", 6: "Q2D_EDEVICE", 7: "Q2D_ESAMPLER", 8: "Q2D_EUNSUPPORTED",
+}
+FP64, FP32 = 0, 1
+TIMER_SWEEP, TIMER_AGG, TIMER_SORT, TIMER_K0, TIMER_CALL = 0, 1, 2, 3, 4
+
+EXPORTS = ("q2d_plan_create", "q2d_plan_destroy", "q2d_plan_set_stream", "q2d_plan_info",
+           "q2d_long_range", "q2d_rbm_step", "q2d_short_range", "q2d_plan_check",
+           "q2d_soe_fit", "q2d_plan_timing_enable", "q2d_plan_timing_read",
+           "q2d_status_string")
+
+
+class Q2DError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__("%s failed: %s (%s)" % (where, STATUS.get(code, code), _status_str(code)))
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("thin", ctypes.c_int32),
+                ("n_max", ctypes.c_int64), ("p_max", ctypes.c_int32),
+                ("validate", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_modes_exact", ctypes.c_int64), ("M", ctypes.c_int32), ("H", ctypes.c_double),
+                ("diag_exact", ctypes.c_double), ("diag_rb", ctypes.c_double),
+                ("soe_k0_self", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libq2d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError("libq2d.so not built: run __graft_entry__.build() or "
+                           "python -m paper_2403_01521_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.q2d_plan_create.argtypes = [dbl, dbl, dbl, dbl, dbl, dbl, i32, dp, dp,
+                                    ctypes.POINTER(_Opts), vp, ctypes.POINTER(vp)]
+    lib.q2d_plan_destroy.argtypes = [vp]
+    lib.q2d_plan_set_stream.argtypes = [vp, vp]
+    lib.q2d_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    lib.q2d_long_range.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    lib.q2d_rbm_step.argtypes = [vp, vp, vp, i64, i32, u64, u64, vp, vp, vp, vp]
+    lib.q2d_short_range.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    lib.q2d_plan_check.argtypes = [vp]
+    lib.q2d_soe_fit.argtypes = [i32, dp, dp, dp]
+    lib.q2d_plan_timing_enable.argtypes = [vp, i32]
+    lib.q2d_plan_timing_read.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.q2d_status_string.argtypes = [ctypes.c_int]
+    lib.q2d_status_string.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "q2d_status_string":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _status_str(code):
+    try:
+        return load_library().q2d_status_string(int(code)).decode()
+    except Exception:  # noqa: BLE001 - diagnostic only
+        return "?"
+
+
+def _check(code, where):
+    if code != 0:
+        raise Q2DError(code, where)
+
+
+def soe_fit(M):
+    """Host SOE of exp(-x^2) with M terms: (w, s, sup_err), complex numpy arrays."""
+    lib = load_library()
+    w = np.zeros(2 * M)
+    s = np.zeros(2 * M)
+    err = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.q2d_soe_fit(M, w.ctypes.data_as(dp), s.ctypes.data_as(dp), ctypes.byref(err)),
+           "q2d_soe_fit")
+    return w[0::2] + 1j * w[1::2], s[0::2] + 1j * s[1::2], err.value
+
+
+def _interleave(z):
+    z = np.asarray(z, dtype=np.complex128)
+    out = np.empty(2 * len(z))
+    out[0::2] = z.real
+    out[1::2] = z.imag
+    return out
+
+
+class Plan:
+    """A solver for one box, Ewald parameter and SOE table (q2d_plan_create)."""
+
+    def __init__(self, box, alpha, w, s, *, rc=0.0, kc=0.0, precision="fp64", n_max,
+                 p_max=0, thin=1, validate=False, stream=None):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        self.box = tuple(float(v) for v in box)
+        self.alpha = float(alpha)
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        w = _interleave(w)
+        s = _interleave(s)
+        opts = _Opts(FP32 if precision == "fp32" else FP64, int(thin), int(n_max), int(p_max),
+                     1 if validate else 0)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        h = ctypes.c_void_p()
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib.q2d_plan_create(self.box[0], self.box[1], self.box[2], self.alpha, float(rc),
+                                   float(kc), len(w) // 2, w.ctypes.data_as(dp),
+                                   s.ctypes.data_as(dp), ctypes.byref(opts),
+                                   ctypes.c_void_p(stream), ctypes.byref(h)), "q2d_plan_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.q2d_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def info(self):
+        inf = _Info()
+        _check(self._lib.q2d_plan_info(self._h, ctypes.byref(inf)), "q2d_plan_info")
+        return dict(n_modes_exact=inf.n_modes_exact, M=inf.M, H=inf.H, diag_exact=inf.diag_exact,
+                    diag_rb=inf.diag_rb, soe_k0_self=inf.soe_k0_self)
+
+    def _sync_stream(self):
+        s = self._torch.cuda.current_stream().cuda_stream
+        if s != self._stream:
+            _check(self._lib.q2d_plan_set_stream(self._h, ctypes.c_void_p(s)), "q2d_plan_set_stream")
+            self._stream = s
+
+    def _prep(self, pos, q):
+        t = self._torch
+        if not (pos.is_cuda and q.is_cuda):
+            raise ValueError("pos and q must be device tensors")
+        if pos.dtype != self.dtype or q.dtype != self.dtype:
+            raise ValueError("dtype must be %s for this plan" % self.dtype)
+        pos = pos.contiguous()
+        q = q.contiguous()
+        if pos.dim() != 2 or pos.shape[1] != 3 or q.shape != (pos.shape[0],):
+            raise ValueError("pos must be (N, 3) and q (N,)")
+        n = pos.shape[0]
+        phi = t.empty(n, dtype=self.dtype, device=pos.device)
+        F = t.empty((n, 3), dtype=self.dtype, device=pos.device)
+        E = t.empty(1, dtype=t.float64, device=pos.device)
+        return pos, q, n, phi, F, E
+
+    def long_range(self, pos, q):
+        """Exact-k SOE long-range sum: (phi, F, E) device tensors."""
+        self._sync_stream()
+        pos, q, n, phi, F, E = self._prep(pos, q)
+        _check(self._lib.q2d_long_range(self._h, pos.data_ptr(), q.data_ptr(), n,
+                                        phi.data_ptr(), F.data_ptr(), E.data_ptr()),
+               "q2d_long_range")
+        return phi, F, E
+
+    def rbm_step(self, pos, q, P, seed, step):
+        """Random-batch step: (phi, F, E, modes[P, 2] int32) device tensors."""
+        self._sync_stream()
+        pos, q, n, phi, F, E = self._prep(pos, q)
+        modes = self._torch.empty((P, 2), dtype=self._torch.int32, device=pos.device)
+        _check(self._lib.q2d_rbm_step(self._h, pos.data_ptr(), q.data_ptr(), n, int(P),
+                                      ctypes.c_uint64(seed), ctypes.c_uint64(step),
+                                      phi.data_ptr(), F.data_ptr(), E.data_ptr(),
+                                      modes.data_ptr()), "q2d_rbm_step")
+        return phi, F, E, modes
+
+    def short_range(self, pos, q):
+        """Real-space erfc sum with cutoff rc: (phi, F, E) device tensors."""
+        self._sync_stream()
+        pos, q, n, phi, F, E = self._prep(pos, q)
+        _check(self._lib.q2d_short_range(self._h, pos.data_ptr(), q.data_ptr(), n,
+                                         phi.data_ptr(), F.data_ptr(), E.data_ptr()),
+               "q2d_short_range")
+        return phi, F, E
+
+    def check(self):
+        """Wait for the stream; return the device-side data status code (0 = ok)."""
+        return int(self._lib.q2d_plan_check(self._h))
+
+    def timing_enable(self, on=True):
+        _check(self._lib.q2d_plan_timing_enable(self._h, 1 if on else 0), "timing_enable")
+
+    def timing_read(self, which):
+        ms = ctypes.c_double(0.0)
+        cnt = ctypes.c_int64(0)
+        _check(self._lib.q2d_plan_timing_read(self._h, int(which), ctypes.byref(ms),
+                                              ctypes.byref(cnt)), "timing_read")
+        return ms.value, cnt.value

@@ -1,0 +1,541 @@
+// C ABI of the library: plan set-up (host FP64 precomputation) and the entry
+// points.  See include/q2d.h for the contract of every function.
+//
+// Host precomputation at plan creation ("Precomputation" of Alg. 1 and Alg. 2):
+//  * the SOE table is checked and split into conjugate pairs;
+//  * H = sum_{k != 0} exp(-k^2/(4 alpha^2)) (Sec. 4.1, eq. hk) by direct lattice sum;
+//  * the exact-k half-lattice mode list 0 < |k| <= k_c with weights
+//    2 (pi/A) exp(-k^2/(4 alpha^2)) (the k and -k terms are complex conjugates);
+//  * the j = i constants D = (pi/A) sum_k e^{-k^2/4a^2} K_k(0) of the SOE
+//    kernel, over |k| <= k_c (exact-k) and over the whole lattice (random batch);
+//  * the k = 0 constants K_0(0) and the linear coefficient (2/sqrt(pi)) sum w_l/s_l.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <new>
+
+#include "q2d_internal.h"
+
+namespace q2d {
+
+q2d_status ensure(Plan *p, Buf &b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return Q2D_OK;
+    if (b.p) {
+        if (hipStreamSynchronize(p->stream) != hipSuccess) return Q2D_EDEVICE;
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    const size_t sz = (bytes + 255) & ~(size_t)255;
+    if (hipMalloc(&b.p, sz) != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return Q2D_ENOMEM;
+    }
+    b.bytes = sz;
+    return Q2D_OK;
+}
+
+void tstart(Plan *p, int which) {
+    if (!p->timing) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, p->stream);
+    p->pend_ev[which].push_back(e);
+}
+
+void tstop(Plan *p, int which) {
+    if (!p->timing) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, p->stream);
+    p->pend_ev[which].push_back(e);
+}
+
+static void timing_flush(Plan *p) {
+    for (int w = 0; w < 5; ++w) {
+        auto &v = p->pend_ev[w];
+        for (size_t i = 0; i + 1 < v.size(); i += 2) {
+            float ms = 0.f;
+            if (hipEventSynchronize(v[i + 1]) == hipSuccess &&
+                hipEventElapsedTime(&ms, v[i], v[i + 1]) == hipSuccess) {
+                p->t_ms[w] += ms;
+                p->t_cnt[w] += 1;
+            }
+        }
+        for (auto e : v) (void)hipEventDestroy(e);
+        v.clear();
+    }
+}
+
+static void free_buf(Buf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+}  // namespace q2d
+
+using namespace q2d;
+using cd = std::complex<double>;
+
+namespace {
+
+const double PI = 3.14159265358979323846;
+
+// K_k(0) of the SOE pair kernel (eq. SOEphi at z = 0, Gaussian factor removed)
+double soe_K0_at(double k, double alpha, const std::vector<cd> &w, const std::vector<cd> &s) {
+    cd acc = 0.0;
+    for (size_t l = 0; l < w.size(); ++l) {
+        const cd b = alpha * s[l];
+        acc += w[l] * (2.0 * b - 2.0 * k) / (b * b - k * k);
+    }
+    return (2.0 * alpha / (std::sqrt(PI) * k) * acc).real();
+}
+
+struct Fit {
+    std::vector<cd> w, s;
+};
+
+// Midpoint rule on Weideman's optimised Talbot contour
+//   z(t) = n (sigma + mu t cot(a t) + i nu t), t in (-pi, pi),
+// for exp(-x^2) = (1/2 pi i) int e^z sqrt(pi/z) exp(-2 sqrt(z) |x|) dz.
+Fit talbot(int M, double scale) {
+    const double sg = -0.6122, mu = 0.5017, a = 0.6407, nu = 0.2645;
+    const double h = 2.0 * PI / M, n = M * scale;
+    Fit f;
+    for (int j = 0; j < M; ++j) {
+        const double t = -PI + (j + 0.5) * h;
+        const cd z = n * cd(sg + mu * t / std::tan(a * t), nu * t);
+        const double st = std::sin(a * t);
+        const cd dz = n * cd(mu * (1.0 / std::tan(a * t) - a * t / (st * st)), nu);
+        const cd w = h / (2.0 * PI * cd(0, 1)) * std::exp(z) * std::sqrt(PI / z) * dz;
+        f.w.push_back(w);
+        f.s.push_back(2.0 * std::sqrt(z));
+    }
+    return f;
+}
+
+double sup_err(const Fit &f, int npts) {
+    double e = 0.0;
+    for (int i = 0; i <= npts; ++i) {
+        // dense on [0, 12], sparse on [12, 200]
+        const double x = i < npts * 9 / 10 ? 12.0 * i / (npts * 9 / 10)
+                                           : 12.0 + 188.0 * (i - npts * 9 / 10) / (npts / 10);
+        cd v = 0.0;
+        for (size_t l = 0; l < f.w.size(); ++l) v += f.w[l] * std::exp(-f.s[l] * x);
+        e = std::max(e, std::fabs(v.real() - std::exp(-x * x)));
+    }
+    return e;
+}
+
+int first_error(int bits) {
+    const int order[] = {Q2D_EOUTOFBOX, Q2D_ENONNEUTRAL, Q2D_ESAMPLER};
+    for (int c : order)
+        if (bits & (1 << c)) return c;
+    return Q2D_OK;
+}
+
+__global__ void k_zero_status(int *st, double *qs) {
+    st[0] = 0;
+    qs[0] = 0.0;
+    qs[1] = 0.0;
+}
+
+__global__ void k_modes_out(const int32_t *modes, int P, int p_pad, int32_t *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) {
+        out[2 * i] = modes[i];
+        out[2 * i + 1] = modes[p_pad + i];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *q2d_status_string(q2d_status st) {
+    switch (st) {
+        case Q2D_OK: return "ok";
+        case Q2D_EINVAL: return "invalid argument";
+        case Q2D_ENONNEUTRAL: return "system is not charge neutral";
+        case Q2D_EOUTOFBOX: return "particle outside [0, Lz] in z or non-finite input";
+        case Q2D_ENOMEM: return "out of memory";
+        case Q2D_ECAPACITY: return "size exceeds the plan's capacity";
+        case Q2D_EDEVICE: return "HIP runtime error";
+        case Q2D_ESAMPLER: return "mode sampler found no non-zero proposal";
+        case Q2D_EUNSUPPORTED: return "plan was created without support for this call";
+    }
+    return "unknown status";
+}
+
+q2d_status q2d_soe_fit(int32_t M, double *w, double *s, double *sup_error) {
+    if (!w || !s || M < 2 || M > 64 || (M % 2)) return Q2D_EINVAL;
+    Fit best;
+    double be = 1e300;
+    for (int i = 0; i <= 40; ++i) {
+        const double sc = 0.6 + 0.02 * i;
+        Fit f = talbot(M, sc);
+        const double e = sup_err(f, 4000);
+        if (e < be) {
+            be = e;
+            best = f;
+        }
+    }
+    for (int l = 0; l < M; ++l) {
+        w[2 * l] = best.w[l].real();
+        w[2 * l + 1] = best.w[l].imag();
+        s[2 * l] = best.s[l].real();
+        s[2 * l + 1] = best.s[l].imag();
+    }
+    if (sup_error) *sup_error = sup_err(best, 40000);
+    return Q2D_OK;
+}
+
+q2d_status q2d_plan_create(double Lx, double Ly, double Lz, double alpha, double r_c, double k_c,
+                           int32_t M, const double *w, const double *s, const q2d_opts *opts,
+                           void *stream, q2d_plan_t *out) {
+    if (!out) return Q2D_EINVAL;
+    *out = nullptr;
+    if (!opts || !w || !s) return Q2D_EINVAL;
+    if (!(Lx > 0 && Ly > 0 && Lz > 0 && alpha > 0) || !std::isfinite(Lx) || !std::isfinite(Ly) ||
+        !std::isfinite(Lz) || !std::isfinite(alpha) || std::isnan(r_c) || std::isnan(k_c))
+        return Q2D_EINVAL;
+    if (M < 2 || M > 2 * MAX_PAIRS || (M % 2)) return Q2D_EINVAL;
+    if (opts->precision != Q2D_FP64 && opts->precision != Q2D_FP32) return Q2D_EINVAL;
+    if (opts->n_max <= 0 || opts->n_max > ((int64_t)1 << 31) - 1 || opts->p_max < 0 ||
+        opts->thin < 0)
+        return Q2D_EINVAL;
+    if (r_c > 0 && r_c > 0.5 * std::min(Lx, Ly)) return Q2D_EINVAL;
+    // SOE table: conjugate-closed, Re s > 0, no real node
+    std::vector<cd> wc(M), sc(M);
+    for (int l = 0; l < M; ++l) {
+        wc[l] = cd(w[2 * l], w[2 * l + 1]);
+        sc[l] = cd(s[2 * l], s[2 * l + 1]);
+        if (!std::isfinite(wc[l].real()) || !std::isfinite(wc[l].imag()) ||
+            !std::isfinite(sc[l].real()) || !std::isfinite(sc[l].imag()))
+            return Q2D_EINVAL;
+        if (!(sc[l].real() > 0) || std::fabs(sc[l].imag()) <= 1e-12 * std::abs(sc[l]))
+            return Q2D_EINVAL;
+    }
+    std::vector<int> partner(M, -1);
+    for (int l = 0; l < M; ++l) {
+        for (int j = 0; j < M; ++j) {
+            if (j == l) continue;
+            if (std::abs(sc[j] - std::conj(sc[l])) <= 1e-10 * std::abs(sc[l]) &&
+                std::abs(wc[j] - std::conj(wc[l])) <= 1e-10 * std::abs(wc[l]) + 1e-300) {
+                partner[l] = j;
+                break;
+            }
+        }
+        if (partner[l] < 0) return Q2D_EINVAL;
+    }
+
+    q2d_plan *p = new (std::nothrow) q2d_plan();
+    if (!p) return Q2D_ENOMEM;
+    p->Lx = Lx;
+    p->Ly = Ly;
+    p->Lz = Lz;
+    p->alpha = alpha;
+    p->rc = r_c;
+    p->kc = k_c;
+    p->M = M;
+    p->mh = M / 2;
+    p->opts = *opts;
+    if (p->opts.thin <= 0) p->opts.thin = 1;
+    p->fp32 = opts->precision == Q2D_FP32;
+    p->stream = (hipStream_t)stream;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return Q2D_EDEVICE;
+    }
+
+    // pair representatives (Im s > 0) and k = 0 combine coefficients
+    PairParams &pp = p->pp;
+    pp.mh = p->mh;
+    pp.m_all = M;
+    int r = 0;
+    const double sqpi = std::sqrt(PI);
+    for (int l = 0; l < M; ++l) {
+        pp.w_re[l] = wc[l].real();
+        pp.w_im[l] = wc[l].imag();
+        pp.b_re[l] = alpha * sc[l].real();
+        pp.b_im[l] = alpha * sc[l].imag();
+        pp.rep_of[l] = -1;
+        if (sc[l].imag() > 0) {
+            if (r >= MAX_PAIRS) {
+                delete p;
+                return Q2D_EINVAL;
+            }
+            pp.rep_of[l] = r;
+            pp.beta_re[r] = alpha * sc[l].real();
+            pp.beta_im[r] = alpha * sc[l].imag();
+            const cd ws = wc[l] / sqpi;
+            const cd cu = 2.0 * ws / alpha;
+            const cd cv = -2.0 * ws * (2.0 / sc[l]);
+            const cd fu = -2.0 * ws * (sc[l] + 2.0 / sc[l]);
+            const cd fv = 2.0 * ws * (2.0 * alpha);
+            pp.c0u_re[r] = cu.real();
+            pp.c0u_im[r] = cu.imag();
+            pp.c0v_re[r] = cv.real();
+            pp.c0v_im[r] = cv.imag();
+            pp.f0u_re[r] = fu.real();
+            pp.f0u_im[r] = fu.imag();
+            pp.f0v_re[r] = fv.real();
+            pp.f0v_im[r] = fv.imag();
+            ++r;
+        }
+    }
+    if (r != p->mh) {
+        delete p;
+        return Q2D_EINVAL;
+    }
+    cd clin = 0.0, k0s = 0.0;
+    for (int l = 0; l < M; ++l) {
+        clin += wc[l] / sc[l];
+        k0s += wc[l] / (alpha * sqpi);
+    }
+    p->c_lin = 2.0 / sqpi * clin.real();
+    p->k0_self = k0s.real();
+
+    // lattice sums: H and the j = i constants
+    const double A = Lx * Ly;
+    const double kmax = 2.0 * alpha * std::sqrt(std::log(1e18));
+    {
+        const int mxm = (int)std::ceil(kmax * Lx / (2 * PI)), mym = (int)std::ceil(kmax * Ly / (2 * PI));
+        double gx = 0, gy = 0;
+        for (int m = -mxm; m <= mxm; ++m) gx += std::exp(-std::pow(2 * PI * m / Lx, 2) / (4 * alpha * alpha));
+        for (int m = -mym; m <= mym; ++m) gy += std::exp(-std::pow(2 * PI * m / Ly, 2) / (4 * alpha * alpha));
+        p->H = gx * gy - 1.0;
+        double drb = 0.0, dex = 0.0;
+        for (int mx = -mxm; mx <= mxm; ++mx)
+            for (int my = -mym; my <= mym; ++my) {
+                if (mx == 0 && my == 0) continue;
+                const double kx = 2 * PI * mx / Lx, ky = 2 * PI * my / Ly;
+                const double k2 = kx * kx + ky * ky;
+                if (k2 > kmax * kmax) continue;
+                const double k = std::sqrt(k2);
+                const double t = std::exp(-k2 / (4 * alpha * alpha)) * soe_K0_at(k, alpha, wc, sc);
+                drb += t;
+                if (k_c > 0 && k2 <= k_c * k_c) dex += t;
+            }
+        p->diag_rb = PI / A * drb;
+        if (k_c > 0) {
+            // exact-k terms beyond kmax (if k_c > kmax) are below 1e-18 of the first
+            const int ex = (int)std::floor(k_c * Lx / (2 * PI)), ey = (int)std::floor(k_c * Ly / (2 * PI));
+            if (k_c > kmax)
+                for (int mx = -ex; mx <= ex; ++mx)
+                    for (int my = -ey; my <= ey; ++my) {
+                        const double kx = 2 * PI * mx / Lx, ky = 2 * PI * my / Ly;
+                        const double k2 = kx * kx + ky * ky;
+                        if ((mx == 0 && my == 0) || k2 <= kmax * kmax || k2 > k_c * k_c) continue;
+                        const double k = std::sqrt(k2);
+                        dex += std::exp(-k2 / (4 * alpha * alpha)) * soe_K0_at(k, alpha, wc, sc);
+                    }
+            p->diag_exact = PI / A * dex;
+        }
+    }
+
+    q2d_status st = ensure(p, p->status, 64);
+    if (st != Q2D_OK) {
+        q2d_plan_destroy(p);
+        return st;
+    }
+    k_zero_status<<<1, 1, 0, p->stream>>>((int *)p->status.p, (double *)((char *)p->status.p + 16));
+
+    // exact-k half-lattice mode table
+    if (k_c > 0) {
+        std::vector<int32_t> mxv, myv;
+        std::vector<double> wt;
+        const int ex = (int)std::floor(k_c * Lx / (2 * PI)), ey = (int)std::floor(k_c * Ly / (2 * PI));
+        for (int mx = 0; mx <= ex; ++mx)
+            for (int my = (mx == 0 ? 1 : -ey); my <= ey; ++my) {
+                const double kx = 2 * PI * mx / Lx, ky = 2 * PI * my / Ly;
+                const double k2 = kx * kx + ky * ky;
+                if (k2 > k_c * k_c) continue;
+                mxv.push_back(mx);
+                myv.push_back(my);
+                wt.push_back(2.0 * PI / A * std::exp(-k2 / (4 * alpha * alpha)));
+            }
+        p->n_exact = (int64_t)mxv.size();
+        p->n_exact_pad = ((p->n_exact + WAVE - 1) / WAVE) * WAVE;
+        if (p->n_exact > 0) {
+            const int64_t np = p->n_exact_pad;
+            std::vector<int32_t> m2(2 * np, 0);
+            std::vector<double> w2(np, 0.0);
+            for (int64_t i = 0; i < p->n_exact; ++i) {
+                m2[i] = mxv[i];
+                m2[np + i] = myv[i];
+                w2[i] = wt[i];
+            }
+            Buf wbuf;
+            const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+            if ((st = ensure(p, p->exact_modes, m2.size() * sizeof(int32_t))) != Q2D_OK ||
+                (st = ensure(p, p->exact_coef, (size_t)coef_fields(p->mh) * np * tsz)) != Q2D_OK ||
+                (st = ensure(p, wbuf, w2.size() * sizeof(double))) != Q2D_OK) {
+                free_buf(wbuf);
+                q2d_plan_destroy(p);
+                return st;
+            }
+            if (hipMemcpyAsync(p->exact_modes.p, m2.data(), m2.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+                hipMemcpyAsync(wbuf.p, w2.data(), w2.size() * sizeof(double),
+                               hipMemcpyHostToDevice, p->stream) != hipSuccess) {
+                free_buf(wbuf);
+                q2d_plan_destroy(p);
+                return Q2D_EDEVICE;
+            }
+            st = build_mode_coefs(p, (const int32_t *)p->exact_modes.p, p->n_exact, np,
+                                  (const double *)wbuf.p, 0.0, p->exact_coef.p);
+            (void)hipStreamSynchronize(p->stream);
+            free_buf(wbuf);
+            if (st != Q2D_OK) {
+                q2d_plan_destroy(p);
+                return st;
+            }
+        }
+    }
+    if (hipStreamSynchronize(p->stream) != hipSuccess) {
+        q2d_plan_destroy(p);
+        return Q2D_EDEVICE;
+    }
+    *out = p;
+    return Q2D_OK;
+}
+
+q2d_status q2d_plan_destroy(q2d_plan_t p) {
+    if (!p) return Q2D_EINVAL;
+    (void)hipSetDevice(p->device);
+    (void)hipStreamSynchronize(p->stream);
+    for (int w = 0; w < 5; ++w) {
+        for (auto e : p->pend_ev[w]) (void)hipEventDestroy(e);
+        p->pend_ev[w].clear();
+    }
+    Buf *bufs[] = {&p->exact_modes, &p->exact_coef, &p->rb_modes, &p->rb_coef, &p->rb_work,
+                   &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
+                   &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->outk, &p->spans0,
+                   &p->agg0, &p->phi0, &p->fz0, &p->epart, &p->status, &p->cell_start,
+                   &p->cell_count, &p->cell_idx, &p->cell_tmp};
+    for (Buf *b : bufs) free_buf(*b);
+    delete p;
+    return Q2D_OK;
+}
+
+q2d_status q2d_plan_set_stream(q2d_plan_t p, void *stream) {
+    if (!p) return Q2D_EINVAL;
+    p->stream = (hipStream_t)stream;
+    return Q2D_OK;
+}
+
+q2d_status q2d_plan_info(q2d_plan_t p, q2d_info *info) {
+    if (!p || !info) return Q2D_EINVAL;
+    info->n_modes_exact = p->n_exact;
+    info->M = p->M;
+    info->H = p->H;
+    info->diag_exact = p->diag_exact;
+    info->diag_rb = p->diag_rb;
+    info->soe_k0_self = p->k0_self;
+    return Q2D_OK;
+}
+
+static q2d_status check_io(q2d_plan_t p, const void *pos, const void *q, int64_t N) {
+    if (!p) return Q2D_EINVAL;
+    if (N < 0) return Q2D_EINVAL;
+    if (N > 0 && (!pos || !q)) return Q2D_EINVAL;
+    if (N > p->opts.n_max) return Q2D_ECAPACITY;
+    if (hipSetDevice(p->device) != hipSuccess) return Q2D_EDEVICE;
+    return Q2D_OK;
+}
+
+q2d_status q2d_long_range(q2d_plan_t p, const void *pos, const void *q, int64_t N, void *phi,
+                          void *F, double *E) {
+    q2d_status st = check_io(p, pos, q, N);
+    if (st != Q2D_OK) return st;
+    if (!(p->kc > 0)) return Q2D_EUNSUPPORTED;
+    tstart(p, 4);
+    int nch = 0;
+    if (N > 0) {
+        if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
+        if (p->n_exact > 0 &&
+            (st = kmodes_run(p, N, (const int32_t *)p->exact_modes.p, p->exact_coef.p,
+                             p->n_exact_pad, 0, p->n_exact, false, &nch)) != Q2D_OK)
+            return st;
+        if ((st = k0_run(p, N)) != Q2D_OK) return st;
+    }
+    st = epilogue(p, N, nch, p->diag_exact, q, phi, F, E);
+    tstop(p, 4);
+    return st;
+}
+
+q2d_status q2d_rbm_step(q2d_plan_t p, const void *pos, const void *q, int64_t N, int32_t P,
+                        uint64_t seed, uint64_t step, void *phi, void *F, double *E,
+                        int32_t *modes_out) {
+    q2d_status st = check_io(p, pos, q, N);
+    if (st != Q2D_OK) return st;
+    if (P < 1) return Q2D_EINVAL;
+    if (p->opts.p_max <= 0) return Q2D_EUNSUPPORTED;
+    if (P > p->opts.p_max) return Q2D_ECAPACITY;
+    tstart(p, 4);
+    if ((st = sample_modes(p, P, seed, step)) != Q2D_OK) return st;
+    const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
+    if (modes_out)
+        k_modes_out<<<(P + 255) / 256, 256, 0, p->stream>>>((const int32_t *)p->rb_modes.p, P, p_pad,
+                                                            modes_out);
+    int nch = 0;
+    if (N > 0) {
+        if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
+        if ((st = kmodes_run(p, N, (const int32_t *)p->rb_modes.p, p->rb_coef.p, p_pad, 0, P,
+                             false, &nch)) != Q2D_OK)
+            return st;
+        if ((st = k0_run(p, N)) != Q2D_OK) return st;
+    }
+    st = epilogue(p, N, nch, p->diag_rb, q, phi, F, E);
+    tstop(p, 4);
+    return st;
+}
+
+q2d_status q2d_short_range(q2d_plan_t p, const void *pos, const void *q, int64_t N, void *phi,
+                           void *F, double *E) {
+    q2d_status st = check_io(p, pos, q, N);
+    if (st != Q2D_OK) return st;
+    if (!(p->rc > 0)) return Q2D_EUNSUPPORTED;
+    if (N == 0) return epilogue(p, 0, 0, 0.0, q, nullptr, nullptr, E);
+    return short_range_run(p, pos, q, N, phi, F, E);
+}
+
+q2d_status q2d_plan_check(q2d_plan_t p) {
+    if (!p) return Q2D_EINVAL;
+    if (hipSetDevice(p->device) != hipSuccess) return Q2D_EDEVICE;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return Q2D_EDEVICE;
+    int bits = 0;
+    if (hipMemcpy(&bits, p->status.p, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return Q2D_EDEVICE;
+    k_zero_status<<<1, 1, 0, p->stream>>>((int *)p->status.p, (double *)((char *)p->status.p + 16));
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return Q2D_EDEVICE;
+    return (q2d_status)first_error(bits);
+}
+
+q2d_status q2d_plan_timing_enable(q2d_plan_t p, int32_t enable) {
+    if (!p) return Q2D_EINVAL;
+    timing_flush(p);
+    for (int w = 0; w < 5; ++w) {
+        p->t_ms[w] = 0;
+        p->t_cnt[w] = 0;
+    }
+    p->timing = enable != 0;
+    return Q2D_OK;
+}
+
+q2d_status q2d_plan_timing_read(q2d_plan_t p, int32_t which, double *ms_total, int64_t *count) {
+    if (!p || which < 0 || which > 4 || !ms_total || !count) return Q2D_EINVAL;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return Q2D_EDEVICE;
+    timing_flush(p);
+    *ms_total = p->t_ms[which];
+    *count = p->t_cnt[which];
+    return Q2D_OK;
+}
+
+}  // extern "C"

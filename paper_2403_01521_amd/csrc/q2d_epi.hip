@@ -1,0 +1,101 @@
+// Epilogue: sum the parts of the long-range potential and force in sorted
+// order, scatter them back to input order, and reduce the energy in FP64.
+//   phi_i = sum_k phi^k_i + q_i D + phi^0_i - 2 alpha q_i / sqrt(pi)   (Sec. 2.2, eq. self)
+//   F_i   = q_i (sum_k force parts) + F^0_i
+//   E     = 1/2 sum_i q_i phi_i                                        (pair energy, Sec. 2.1)
+// D is the configuration-independent j = i constant of the k != 0 modes.
+// The energy is reduced in a fixed order (block tree, then one block over the
+// block partials), so repeated calls give identical bits.
+#include "q2d_internal.h"
+
+namespace q2d {
+
+namespace {
+
+constexpr int EPI_THREADS = 256;
+
+template <typename T>
+__global__ __launch_bounds__(EPI_THREADS) void k_epi(int64_t N, int nchunks,
+                                                     const T *__restrict__ outk,
+                                                     const T *__restrict__ qs,
+                                                     const double *__restrict__ phi0,
+                                                     const double *__restrict__ fz0,
+                                                     const int32_t *__restrict__ perm, double diag,
+                                                     double self_c, T *__restrict__ phi,
+                                                     T *__restrict__ F, double *__restrict__ epart) {
+    __shared__ double red[EPI_THREADS];
+    const int64_t i = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
+    double e = 0.0;
+    if (i < N) {
+        double o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+        for (int c = 0; c < nchunks; ++c) {
+            const T *o = outk + ((int64_t)c * N + i) * 4;
+            o0 += (double)o[0];
+            o1 += (double)o[1];
+            o2 += (double)o[2];
+            o3 += (double)o[3];
+        }
+        const double q = (double)qs[i];
+        const double ph = o0 + q * diag + phi0[i] - self_c * q;
+        const int64_t orig = perm[i];
+        if (phi) phi[orig] = (T)ph;
+        if (F) {
+            F[3 * orig] = (T)(q * o1);
+            F[3 * orig + 1] = (T)(q * o2);
+            F[3 * orig + 2] = (T)(q * o3 + fz0[i]);
+        }
+        e = q * ph;
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int h = EPI_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(EPI_THREADS) void k_energy(const double *__restrict__ epart,
+                                                        int nparts, double *__restrict__ E) {
+    __shared__ double red[EPI_THREADS];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += EPI_THREADS) s += epart[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = EPI_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) E[0] = 0.5 * red[0];
+}
+
+__global__ void k_set_zero(double *E) { E[0] = 0.0; }
+
+}  // namespace
+
+q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, const void *q, void *phi,
+                    void *F, double *E) {
+    (void)q;
+    if (N <= 0) {
+        if (E) k_set_zero<<<1, 1, 0, p->stream>>>(E);
+        return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+    }
+    const int nb = (int)((N + EPI_THREADS - 1) / EPI_THREADS);
+    q2d_status st;
+    if ((st = ensure(p, p->epart, (size_t)nb * sizeof(double))) != Q2D_OK) return st;
+    const double self_c = 2.0 * p->alpha / sqrt(3.14159265358979323846);
+    if (p->fp32)
+        k_epi<float><<<nb, EPI_THREADS, 0, p->stream>>>(
+            N, n_chunks, (const float *)p->outk.p, (const float *)p->s_q.p,
+            (const double *)p->phi0.p, (const double *)p->fz0.p, p->perm, diag, self_c,
+            (float *)phi, (float *)F, (double *)p->epart.p);
+    else
+        k_epi<double><<<nb, EPI_THREADS, 0, p->stream>>>(
+            N, n_chunks, (const double *)p->outk.p, (const double *)p->s_q.p,
+            (const double *)p->phi0.p, (const double *)p->fz0.p, p->perm, diag, self_c,
+            (double *)phi, (double *)F, (double *)p->epart.p);
+    if (E) k_energy<<<1, EPI_THREADS, 0, p->stream>>>((const double *)p->epart.p, nb, E);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+}  // namespace q2d

@@ -1,0 +1,151 @@
+// Internal declarations of the q2d library (host plan, scratch, kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/q2d.h"
+
+namespace q2d {
+
+constexpr int WAVE = 64;
+constexpr int MAX_PAIRS = 16;  // M <= 32 SOE terms (conjugate pairs)
+
+// ----------------------------------------------------------------------------
+// small complex helper used on host and device
+// ----------------------------------------------------------------------------
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ inline cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__host__ __device__ inline cx<T> cadd(cx<T> a, cx<T> b) {
+    return {a.re + b.re, a.im + b.im};
+}
+
+// SOE pair representatives passed to kernels by value.
+struct PairParams {
+    int mh;                       // number of conjugate pairs used
+    double beta_re[MAX_PAIRS];    // beta_l = alpha s_l, representative with Im > 0
+    double beta_im[MAX_PAIRS];
+    // k = 0 combine coefficients (eq. 32 / eq. dzphi_0), pair-summed (x2):
+    double c0u_re[MAX_PAIRS], c0u_im[MAX_PAIRS];  // phi: coefficient of U
+    double c0v_re[MAX_PAIRS], c0v_im[MAX_PAIRS];  // phi: coefficient of V
+    double f0u_re[MAX_PAIRS], f0u_im[MAX_PAIRS];  // dz:  coefficient of U
+    double f0v_re[MAX_PAIRS], f0v_im[MAX_PAIRS];  // dz:  coefficient of V
+    // per-term SOE data for mode coefficients (all M terms)
+    int m_all;
+    double w_re[2 * MAX_PAIRS], w_im[2 * MAX_PAIRS];
+    double b_re[2 * MAX_PAIRS], b_im[2 * MAX_PAIRS];   // beta of every term
+    int rep_of[2 * MAX_PAIRS];                          // pair index if representative, else -1
+};
+
+// Number of real fields per mode in a coefficient table:
+//   0 kx, 1 ky, 2 k, 3 omega, 4 ak, 5 akd, then per pair l: al.re al.im ald.re ald.im
+inline int coef_fields(int mh) { return 6 + 4 * mh; }
+
+// ----------------------------------------------------------------------------
+// device scratch buffer that grows on demand
+// ----------------------------------------------------------------------------
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Plan {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double Lx, Ly, Lz, alpha, rc, kc;
+    int M = 0, mh = 0;
+    q2d_opts opts{};
+    bool fp32 = false;
+    PairParams pp{};
+    double H = 0, diag_exact = 0, diag_rb = 0, k0_self = 0, c_lin = 0;
+
+    // exact-k half-lattice mode list (device) and its coefficient table
+    int64_t n_exact = 0, n_exact_pad = 0;
+    Buf exact_modes;  // int32 [2][n_exact_pad]
+    Buf exact_coef;   // T [fields][n_exact_pad]
+
+    // random-batch tables
+    Buf rb_modes;     // int32 [2][p_pad]
+    Buf rb_coef;      // T [fields][p_pad]
+    Buf rb_work;      // sampler work arrays
+
+    // sorting and sorted data
+    Buf keys_a, keys_b, vals_a, vals_b, hist;
+    Buf s_ux, s_uy, s_z, s_q;  // sorted SoA
+    int32_t *perm = nullptr;   // points into vals_a or vals_b after the sort
+
+    // k != 0 scans
+    Buf spans;                 // FP64 complex W,G per (segment, pair)
+    Buf agg;                   // aggregates / carries (both directions)
+    Buf outk;                  // per-chunk per-particle outputs (T x 4)
+
+    // k = 0 scans
+    Buf spans0, agg0;
+    Buf phi0, fz0;             // FP64 per particle (sorted order)
+
+    // epilogue and status
+    Buf epart;
+    Buf status;                // int32 device status word
+
+    // short range
+    Buf cell_start, cell_count, cell_idx, cell_tmp;
+
+    // timing
+    bool timing = false;
+    hipEvent_t ev[5][2]{};
+    double t_ms[5]{};
+    int64_t t_cnt[5]{};
+    std::vector<hipEvent_t> pend_ev[5];
+};
+
+// growth helper: ensure buffer holds at least `bytes`
+q2d_status ensure(Plan *p, Buf &b, size_t bytes);
+
+// timing helpers
+void tstart(Plan *p, int which);
+void tstop(Plan *p, int which);
+
+// ----------------------------------------------------------------------------
+// launchers (each enqueues on p->stream)
+// ----------------------------------------------------------------------------
+// validation + key staging + stable radix sort by z + gather of sorted SoA
+q2d_status sort_and_stage(Plan *p, const void *pos, const void *q, int64_t N);
+
+// device coefficient tables for a list of modes
+q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_pad,
+                            const double *weights_dev, double weight_const, void *coef);
+
+// random-batch sampler: writes p->rb_modes and p->rb_coef for P modes
+q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step);
+
+// k != 0 part over a mode table: accumulates per-particle outputs into outk
+q2d_status kmodes_run(Plan *p, int64_t N, const int32_t *modes, const void *coef,
+                      int64_t coef_stride, int64_t mode_off, int64_t n_modes, bool accumulate,
+                      int *n_chunks_out);
+
+// k = 0 term: writes p->phi0, p->fz0 (FP64, sorted order)
+q2d_status k0_run(Plan *p, int64_t N);
+
+// combine, unsort, energy
+q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, const void *q, void *phi,
+                    void *F, double *E);
+
+// short range
+q2d_status short_range_run(Plan *p, const void *pos, const void *q, int64_t N, void *phi, void *F,
+                           double *E);
+
+}  // namespace q2d
+
+// The opaque handle of the C ABI is the plan itself.
+struct q2d_plan : public q2d::Plan {};

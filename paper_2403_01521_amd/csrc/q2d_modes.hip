@@ -1,0 +1,221 @@
+// Fourier-mode tables: per-mode SOE coefficients and the random-batch sampler.
+//
+// Coefficients (Sec. 3.2, eq. SOEphi; App. E, eq. z-der).  For a mode k with
+// |k| = k the pair kernel without its Gaussian factor is
+//   K_k(z) = (2 alpha/(sqrt(pi) k)) sum_l w_l (2 beta_l e^{-kz} - 2k e^{-beta_l z}) / (beta_l^2 - k^2)
+//          = a_k e^{-kz} + sum_l a_l e^{-beta_l z},   beta_l = alpha s_l,
+// so with c_l = (2 alpha/(sqrt(pi) k)) w_l / (beta_l^2 - k^2):
+//   a_k = Re sum_l 2 beta_l c_l,   a_l = -2 k c_l,
+// and its derivative K'_k(z) = -k a_k e^{-kz} + sum_l (2 k beta_l c_l) e^{-beta_l z}.
+// Conjugate SOE terms give conjugate scans for real inputs, so each pair is
+// carried once with doubled coefficients (the sum of a term and its conjugate
+// is twice its real part).
+//
+// Sampler (Sec. 4.1 and App. G): importance sampling of k != 0 from
+// h(k) = exp(-k^2/(4 alpha^2))/H by an independence Metropolis chain whose
+// proposal rounds a Gaussian draw m* ~ N(0, (alpha L)^2/(2 pi^2)) per axis;
+// random numbers from Philox4x32-10.  Proposals are independent of the chain
+// state, so they are drawn in parallel and only the accept/reject walk runs
+// sequentially.
+#include "q2d_internal.h"
+
+namespace q2d {
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mode_coefs(const int32_t *__restrict__ modes, int64_t n,
+                                                    int64_t n_pad, const double *weights,
+                                                    double weight_const, PairParams pp,
+                                                    double alpha, double Lx, double Ly,
+                                                    T *__restrict__ coef) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_pad) return;
+    const int nf = 6 + 4 * pp.mh;
+    if (m >= n) {
+        for (int f = 0; f < nf; ++f) coef[f * n_pad + m] = (T)0;
+        return;
+    }
+    const double PI = 3.14159265358979323846;
+    const double kx = 2.0 * PI * modes[m] / Lx;
+    const double ky = 2.0 * PI * modes[n_pad + m] / Ly;
+    const double k = sqrt(kx * kx + ky * ky);
+    const double om = weights ? weights[m] : weight_const;
+    const double pre = 2.0 * alpha / (sqrt(PI) * k);
+    double ak = 0.0;
+    for (int l = 0; l < pp.m_all; ++l) {
+        const cx<double> b{pp.b_re[l], pp.b_im[l]};
+        const cx<double> w{pp.w_re[l], pp.w_im[l]};
+        cx<double> den = cmul(b, b);
+        den.re -= k * k;
+        // c = pre * w / den
+        const double dd = den.re * den.re + den.im * den.im;
+        const cx<double> wd{(w.re * den.re + w.im * den.im) / dd, (w.im * den.re - w.re * den.im) / dd};
+        const cx<double> c{pre * wd.re, pre * wd.im};
+        const cx<double> bc = cmul(b, c);
+        ak += 2.0 * bc.re;
+        const int r = pp.rep_of[l];
+        if (r >= 0) {
+            // pair representative: doubled a_l = -2 k c and doubled 2 k beta c
+            coef[(6 + 4 * r + 0) * n_pad + m] = (T)(2.0 * (-2.0 * k * c.re));
+            coef[(6 + 4 * r + 1) * n_pad + m] = (T)(2.0 * (-2.0 * k * c.im));
+            coef[(6 + 4 * r + 2) * n_pad + m] = (T)(2.0 * (2.0 * k * bc.re));
+            coef[(6 + 4 * r + 3) * n_pad + m] = (T)(2.0 * (2.0 * k * bc.im));
+        }
+    }
+    coef[0 * n_pad + m] = (T)kx;
+    coef[1 * n_pad + m] = (T)ky;
+    coef[2 * n_pad + m] = (T)k;
+    coef[3 * n_pad + m] = (T)om;
+    coef[4 * n_pad + m] = (T)ak;
+    coef[5 * n_pad + m] = (T)(-k * ak);
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): multipliers 0xD2511F53, 0xCD9E8D57,
+// key increments 0x9E3779B9, 0xBB67AE85.
+__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// uniform in (0, 1) from 53 bits of two words
+__device__ inline double u53(uint32_t a, uint32_t b) {
+    const uint64_t v = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
+    return ((double)v + 0.5) * 0x1p-53;
+}
+
+// proposal probability of one axis (App. G), as differences of erfc in the tails
+__device__ inline double q_axis(int m, double aL) {
+    const double PI = 3.14159265358979323846;
+    const int am = m < 0 ? -m : m;
+    if (am == 0) return erf(PI / (2.0 * aL));
+    return 0.5 * (erfc(PI * (2 * am - 1) / (2.0 * aL)) - erfc(PI * (2 * am + 1) / (2.0 * aL)));
+}
+
+// target over proposal, unnormalised; 0 at m = (0, 0)
+__device__ inline double mh_weight(int mx, int my, double alpha, double Lx, double Ly) {
+    if (mx == 0 && my == 0) return 0.0;
+    const double PI = 3.14159265358979323846;
+    const double kx = 2.0 * PI * mx / Lx, ky = 2.0 * PI * my / Ly;
+    const double h = exp(-(kx * kx + ky * ky) / (4.0 * alpha * alpha));
+    return h / (q_axis(mx, alpha * Lx) * q_axis(my, alpha * Ly));
+}
+
+constexpr int SAMPLER_RESERVE = 64;
+
+// One block: parallel proposals, then the sequential accept/reject walk.
+__global__ __launch_bounds__(1024) void k_sample(int P, int D, uint64_t seed, uint64_t step,
+                                                 double alpha, double Lx, double Ly,
+                                                 int32_t *__restrict__ prop,
+                                                 double *__restrict__ wgt,
+                                                 double *__restrict__ uacc,
+                                                 int32_t *__restrict__ modes, int p_pad,
+                                                 int *status) {
+    const int n = SAMPLER_RESERVE + P * D;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t s0 = (uint32_t)step, s1 = (uint32_t)(step >> 32);
+    const double PI = 3.14159265358979323846;
+    const double sx = alpha * Lx / (PI * sqrt(2.0)), sy = alpha * Ly / (PI * sqrt(2.0));
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        uint32_t c[4] = {(uint32_t)e, s0, s1, 0u};
+        philox10(c, k0, k1);
+        const double u1 = u53(c[0], c[1]), u2 = u53(c[2], c[3]);
+        const double R = sqrt(-2.0 * log(u1));
+        const double n1 = R * cos(2.0 * PI * u2), n2 = R * sin(2.0 * PI * u2);
+        const int mx = (int)floor(sx * n1 + 0.5), my = (int)floor(sy * n2 + 0.5);
+        uint32_t a[4] = {(uint32_t)e, s0, s1, 1u};
+        philox10(a, k0, k1);
+        prop[2 * e] = mx;
+        prop[2 * e + 1] = my;
+        wgt[e] = mh_weight(mx, my, alpha, Lx, Ly);
+        uacc[e] = u53(a[0], a[1]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int e0 = -1;
+        for (int e = 0; e < SAMPLER_RESERVE; ++e)
+            if (prop[2 * e] != 0 || prop[2 * e + 1] != 0) {
+                e0 = e;
+                break;
+            }
+        if (e0 < 0) {
+            atomicOr(status, 1 << Q2D_ESAMPLER);
+            e0 = 0;
+        }
+        int cx_ = prop[2 * e0], cy_ = prop[2 * e0 + 1];
+        double wc = wgt[e0];
+        for (int t = 1; t <= P * D; ++t) {
+            const int e = e0 + t;
+            if (uacc[e] < wgt[e] / wc) {
+                cx_ = prop[2 * e];
+                cy_ = prop[2 * e + 1];
+                wc = wgt[e];
+            }
+            if (t % D == 0) {
+                const int pidx = t / D - 1;
+                modes[pidx] = cx_;
+                modes[p_pad + pidx] = cy_;
+            }
+        }
+    }
+    __syncthreads();
+    // padding modes
+    for (int i = P + threadIdx.x; i < p_pad; i += blockDim.x) {
+        modes[i] = 0;
+        modes[p_pad + i] = 0;
+    }
+}
+
+}  // namespace
+
+q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_pad,
+                            const double *weights_dev, double weight_const, void *coef) {
+    if (n_pad <= 0) return Q2D_OK;
+    const int nb = (int)((n_pad + 255) / 256);
+    if (p->fp32)
+        k_mode_coefs<float><<<nb, 256, 0, p->stream>>>(modes, n, n_pad, weights_dev, weight_const,
+                                                       p->pp, p->alpha, p->Lx, p->Ly,
+                                                       (float *)coef);
+    else
+        k_mode_coefs<double><<<nb, 256, 0, p->stream>>>(modes, n, n_pad, weights_dev,
+                                                        weight_const, p->pp, p->alpha, p->Lx,
+                                                        p->Ly, (double *)coef);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step) {
+    const int D = p->opts.thin > 0 ? p->opts.thin : 1;
+    const int n = SAMPLER_RESERVE + P * D;
+    const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
+    q2d_status st;
+    if ((st = ensure(p, p->rb_work, (size_t)n * (2 * sizeof(int32_t) + 2 * sizeof(double)))) !=
+        Q2D_OK)
+        return st;
+    if ((st = ensure(p, p->rb_modes, (size_t)2 * p_pad * sizeof(int32_t))) != Q2D_OK) return st;
+    const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+    if ((st = ensure(p, p->rb_coef, (size_t)coef_fields(p->mh) * p_pad * tsz)) != Q2D_OK) return st;
+    int32_t *prop = (int32_t *)p->rb_work.p;
+    double *wgt = (double *)((char *)p->rb_work.p + (size_t)n * 2 * sizeof(int32_t));
+    double *uacc = wgt + n;
+    k_sample<<<1, 1024, 0, p->stream>>>(P, D, seed, step, p->alpha, p->Lx, p->Ly, prop, wgt, uacc,
+                                         (int32_t *)p->rb_modes.p, p_pad, (int *)p->status.p);
+    if (hipGetLastError() != hipSuccess) return Q2D_EDEVICE;
+    const double PI = 3.14159265358979323846;
+    return build_mode_coefs(p, (const int32_t *)p->rb_modes.p, P, p_pad, nullptr,
+                            PI / (p->Lx * p->Ly) * p->H / P, p->rb_coef.p);
+}
+
+}  // namespace q2d

@@ -1,0 +1,695 @@
+// Fourier modes k != 0: batched forward/backward z-ordered prefix scans.
+//
+// For one mode k and one exponent beta (beta = k or beta = alpha s_l) the
+// recursion of Sec. 3.2 (eq. S, eq. 35) computes, over particles sorted by z,
+//   T_i = sum_{j<i} b_j e^{-beta (z_i - z_j)},   B_i = sum_{j>i} b_j e^{-beta (z_j - z_i)}
+// through the bounded ratios e^{-beta (z_i - z_{i-1})}.  With real sources
+// x_j = q_j cos(k.rho_j) and y_j = q_j sin(k.rho_j) and the pair kernel
+// K_k(z) = sum_beta a_beta e^{-beta z} (coefficients in q2d_modes.hip):
+//   X_i = sum_{j != i} x_j K_k(|z_ij|) = sum_beta Re a_beta (T^x + B^x)
+//   X'_i = sum_{j != i} x_j sgn(z_i - z_j) K'_k(|z_ij|) = sum_beta Re a'_beta (T^x - B^x)
+// (Y, Y' likewise), and with c_i, s_i = cos, sin(k.rho_i):
+//   phi_i  += omega (c_i X_i + s_i Y_i)                  (eq. SOEphi, real part)
+//   F_rho  += omega q_i k_vec (s_i X_i - c_i Y_i)         (App. E, d/d rho)
+//   F_z    -= omega q_i (c_i X'_i + s_i Y'_i)             (App. E, eq. z-der)
+//
+// GPU layout (one wave per work-group):
+//  * lanes are modes: 64 modes of a batch share each particle, so the
+//    particle data and the SOE decays e^{-beta_l dz} (mode independent) are
+//    computed once per 64-particle block into LDS and read as broadcasts;
+//  * the particle axis is cut into segments of S consecutive sorted
+//    particles; a wave sweeps one segment sequentially (the recursion) for
+//    its modes, after (1) an aggregate pass gives every segment's total
+//    contribution referenced to its end (forward) and start (backward), and
+//    (2) an FP64 scan over segments turns aggregates into carry-ins.  Every
+//    cross-segment factor is one exponential of a z difference, never a long
+//    product of rounded ratios;
+//  * the per-particle results are reduced over the 64 mode lanes through a
+//    padded LDS transpose in a fixed order (deterministic).
+#include "q2d_internal.h"
+
+namespace q2d {
+
+namespace {
+
+template <typename T>
+struct Tr;
+template <>
+struct Tr<float> {
+    using U = uint32_t;  // x/Lx as a 32-bit fixed-point fraction of a turn
+};
+template <>
+struct Tr<double> {
+    using U = double;    // x/Lx as a double in [0, 1)
+};
+
+// sin, cos of 2 pi (mx ux + my uy)
+__device__ inline void phase_sc(int mx, int my, uint32_t ux, uint32_t uy, float &s, float &c) {
+    const uint32_t ph = (uint32_t)mx * ux + (uint32_t)my * uy;  // exact modulo one turn
+    sincospif((float)(int32_t)ph * 0x1p-31f, &s, &c);
+}
+__device__ inline void phase_sc(int mx, int my, double ux, double uy, double &s, double &c) {
+    double r = fma((double)mx, ux, (double)my * uy);
+    r -= rint(r);
+    sincospi(2.0 * r, &s, &c);
+}
+
+// exp(-(br + i bi) t)
+__device__ inline cx<float> cexpm(float br, float bi, float t) {
+    const float m = expf(-br * t);
+    float s, c;
+    sincosf(bi * t, &s, &c);
+    return {m * c, -m * s};
+}
+__device__ inline cx<double> cexpm(double br, double bi, double t) {
+    const double ar = br * t, ai = bi * t;
+    if (fabs(ar) + fabs(ai) < 0.015625) {
+        // e^{-x}, |x| < 2^-6: Taylor to x^7 (remainder < 1e-19)
+        const double xr = ar, xi = ai;
+        double pr = 1.0 / 5040.0, pi = 0.0;
+        const double cs[7] = {1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0, 0.5, 1.0, 1.0};
+        const double sg[7] = {1, -1, 1, -1, 1, -1, 1};
+        // p(x) = sum_n (-x)^n / n!: Horner in (-x)
+#pragma unroll
+        for (int n = 0; n < 7; ++n) {
+            const double nr = -(pr * xr - pi * xi), ni = -(pr * xi + pi * xr);
+            pr = nr + cs[n];
+            pi = ni;
+            (void)sg;
+        }
+        return {pr, pi};
+    }
+    const double m = exp(-ar);
+    double s, c;
+    sincos(ai, &s, &c);
+    return {m * c, -m * s};
+}
+__device__ inline float expm_real(float k, float t) { return __expf(-k * t); }
+__device__ inline double expm_real(double k, double t) { return exp(-k * t); }
+
+template <typename T>
+struct KArgs {
+    int64_t N;
+    int S, nseg;
+    const typename Tr<T>::U *ux, *uy;
+    const T *z, *q;
+    const int32_t *modes;
+    int64_t mstride;  // my of mode m at modes[mstride + m]
+    const T *coef;
+    int64_t cstride;  // field f of mode m at coef[f * cstride + m]
+    int64_t moff;
+    int nmodes, ngroups, gpc, gpad;
+    T bre[MAX_PAIRS], bim[MAX_PAIRS];
+    cx<T> *agg;  // [2 dirs][nseg][MH+1 slots][2 inputs][gpad]
+    T *outk;     // [chunks][N][4]
+    int accumulate;
+};
+
+template <int MH>
+__device__ inline int64_t agg_idx(int nseg, int gpad, int dir, int seg, int slot, int inp, int m) {
+    return ((((int64_t)dir * nseg + seg) * (MH + 1) + slot) * 2 + inp) * gpad + m;
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: per-segment aggregates (dot products with decays to the ends)
+// ---------------------------------------------------------------------------
+template <typename T, int MH>
+__global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
+    using U = typename Tr<T>::U;
+    const int seg = blockIdx.x, chunk = blockIdx.y, lane = threadIdx.x;
+    const int64_t i0 = (int64_t)seg * a.S;
+    const int64_t i1 = min(i0 + (int64_t)a.S, a.N);
+    __shared__ U c_ux[WAVE], c_uy[WAVE];
+    __shared__ T c_q[WAVE], c_zf[WAVE], c_zb[WAVE];
+    __shared__ cx<T> c_ef[MH][WAVE], c_eb[MH][WAVE];
+    const T zfirst = a.z[i0], zlast = a.z[i1 - 1];
+    const int g0 = chunk * a.gpc, g1 = min(g0 + a.gpc, a.ngroups);
+    for (int g = g0; g < g1; ++g) {
+        const int m = g * WAVE + lane;
+        const bool mv = m < a.nmodes;
+        const int mx = mv ? a.modes[a.moff + m] : 0;
+        const int my = mv ? a.modes[a.mstride + a.moff + m] : 0;
+        const T k = mv ? a.coef[2 * a.cstride + a.moff + m] : (T)0;
+        cx<T> fx[MH], fy[MH], bx[MH], by[MH];
+#pragma unroll
+        for (int l = 0; l < MH; ++l) fx[l] = fy[l] = bx[l] = by[l] = cx<T>{0, 0};
+        T fkx = 0, fky = 0, bkx = 0, bky = 0;
+        for (int64_t ib = i0; ib < i1; ib += WAVE) {
+            const int nb = (int)min((int64_t)WAVE, i1 - ib);
+            __syncthreads();
+            if (lane < nb) {
+                const int64_t p = ib + lane;
+                c_ux[lane] = a.ux[p];
+                c_uy[lane] = a.uy[p];
+                c_q[lane] = a.q[p];
+                const T zp = a.z[p];
+                const T tf = zlast - zp, tb = zp - zfirst;
+                c_zf[lane] = tf;
+                c_zb[lane] = tb;
+#pragma unroll
+                for (int l = 0; l < MH; ++l) {
+                    c_ef[l][lane] = cexpm(a.bre[l], a.bim[l], tf);
+                    c_eb[l][lane] = cexpm(a.bre[l], a.bim[l], tb);
+                }
+            }
+            __syncthreads();
+            for (int j = 0; j < nb; ++j) {
+                T s, c;
+                phase_sc(mx, my, c_ux[j], c_uy[j], s, c);
+                const T x = c_q[j] * c, y = c_q[j] * s;
+                const T ef = expm_real(k, c_zf[j]), eb = expm_real(k, c_zb[j]);
+                fkx += x * ef;
+                fky += y * ef;
+                bkx += x * eb;
+                bky += y * eb;
+#pragma unroll
+                for (int l = 0; l < MH; ++l) {
+                    const cx<T> e = c_ef[l][j];
+                    fx[l].re += x * e.re;
+                    fx[l].im += x * e.im;
+                    fy[l].re += y * e.re;
+                    fy[l].im += y * e.im;
+                    const cx<T> e2 = c_eb[l][j];
+                    bx[l].re += x * e2.re;
+                    bx[l].im += x * e2.im;
+                    by[l].re += y * e2.re;
+                    by[l].im += y * e2.im;
+                }
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < MH; ++l) {
+            a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, l, 0, m)] = fx[l];
+            a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, l, 1, m)] = fy[l];
+            a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, l, 0, m)] = bx[l];
+            a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, l, 1, m)] = by[l];
+        }
+        a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 0, m)] = cx<T>{fkx, 0};
+        a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 1, m)] = cx<T>{fky, 0};
+        a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 0, m)] = cx<T>{bkx, 0};
+        a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 1, m)] = cx<T>{bky, 0};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass 3: the sweep (recursion) of one segment for the lanes' modes
+// ---------------------------------------------------------------------------
+constexpr int SMAX = 512;  // largest segment
+constexpr int SUB = 16;    // particles per lane-reduction round
+
+template <typename T, int MH, int DIR>
+__device__ inline void sweep_dir(const KArgs<T> &a, int seg, int m, int64_t i0, int64_t i1,
+                                 int mx, int my, T kx, T ky, T k, T om, T ak, T akd,
+                                 const T *alr, const T *ali, const T *adr, const T *adi,
+                                 typename Tr<T>::U *c_ux, typename Tr<T>::U *c_uy, T *c_q,
+                                 T *c_dz, cx<T> (*c_d)[WAVE], T (*red)[4][WAVE + 1],
+                                 T (*outl)[4]) {
+    const int lane = threadIdx.x;
+    cx<T> px[MH], py[MH];
+#pragma unroll
+    for (int l = 0; l < MH; ++l) {
+        px[l] = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, seg, l, 0, m)];
+        py[l] = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, seg, l, 1, m)];
+    }
+    T pkx = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, seg, MH, 0, m)].re;
+    T pky = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, seg, MH, 1, m)].re;
+    const int ns = (int)(i1 - i0);
+    const int nblk = (ns + WAVE - 1) / WAVE;
+    for (int bb = 0; bb < nblk; ++bb) {
+        const int blk = DIR ? (nblk - 1 - bb) : bb;
+        const int64_t ib = i0 + (int64_t)blk * WAVE;
+        const int nb = (int)min((int64_t)WAVE, i1 - ib);
+        __syncthreads();
+        if (lane < nb) {
+            const int64_t p = ib + lane;
+            c_ux[lane] = a.ux[p];
+            c_uy[lane] = a.uy[p];
+            c_q[lane] = a.q[p];
+            // gap to the particle below inside this segment (0 at its first one)
+            const T dz = (p > i0) ? a.z[p] - a.z[p - 1] : (T)0;
+            c_dz[lane] = dz;
+#pragma unroll
+            for (int l = 0; l < MH; ++l) c_d[l][lane] = cexpm(a.bre[l], a.bim[l], dz);
+        }
+        __syncthreads();
+        for (int jj = 0; jj < nb; ++jj) {
+            const int j = DIR ? nb - 1 - jj : jj;
+            T s, c;
+            phase_sc(mx, my, c_ux[j], c_uy[j], s, c);
+            const T qj = c_q[j];
+            const T x = qj * c, y = qj * s;
+            const T dk = expm_real(k, c_dz[j]);
+            T X, Y, Xd, Yd;
+            if (DIR == 0) {
+                // T_j = (T_{j-1} + source_{j-1}) e^{-beta dz_j}
+                const T tkx = pkx * dk, tky = pky * dk;
+                X = ak * tkx;
+                Xd = akd * tkx;
+                Y = ak * tky;
+                Yd = akd * tky;
+                pkx = tkx + x;
+                pky = tky + y;
+#pragma unroll
+                for (int l = 0; l < MH; ++l) {
+                    const cx<T> d = c_d[l][j];
+                    const cx<T> tx = cmul(px[l], d), ty = cmul(py[l], d);
+                    X += alr[l] * tx.re - ali[l] * tx.im;
+                    Xd += adr[l] * tx.re - adi[l] * tx.im;
+                    Y += alr[l] * ty.re - ali[l] * ty.im;
+                    Yd += adr[l] * ty.re - adi[l] * ty.im;
+                    px[l] = cx<T>{tx.re + x, tx.im};
+                    py[l] = cx<T>{ty.re + y, ty.im};
+                }
+            } else {
+                // B_j is the pending state; B_{j-1} = (B_j + source_j) e^{-beta dz_j}
+                X = ak * pkx;
+                Xd = akd * pkx;
+                Y = ak * pky;
+                Yd = akd * pky;
+                pkx = (pkx + x) * dk;
+                pky = (pky + y) * dk;
+#pragma unroll
+                for (int l = 0; l < MH; ++l) {
+                    const cx<T> d = c_d[l][j];
+                    X += alr[l] * px[l].re - ali[l] * px[l].im;
+                    Xd += adr[l] * px[l].re - adi[l] * px[l].im;
+                    Y += alr[l] * py[l].re - ali[l] * py[l].im;
+                    Yd += adr[l] * py[l].re - adi[l] * py[l].im;
+                    px[l] = cmul(cx<T>{px[l].re + x, px[l].im}, d);
+                    py[l] = cmul(cx<T>{py[l].re + y, py[l].im}, d);
+                }
+            }
+            const T oq = om * (s * X - c * Y);
+            const int r = jj % SUB;
+            red[r][0][lane] = om * (c * X + s * Y);
+            red[r][1][lane] = kx * oq;
+            red[r][2][lane] = ky * oq;
+            red[r][3][lane] = -om * (c * Xd + s * Yd);
+            if (r == SUB - 1 || jj == nb - 1) {
+                __syncthreads();
+                const int rj = lane >> 2, v = lane & 3;
+                if (rj <= r) {
+                    T sum = 0;
+                    for (int L = 0; L < WAVE; ++L) sum += red[rj][v][L];
+                    const int pj = jj - r + rj;
+                    const int jpart = DIR ? nb - 1 - pj : pj;
+                    outl[(int)(ib - i0) + jpart][v] += sum;
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+template <typename T, int MH>
+__global__ __launch_bounds__(64) void k_sweep(const KArgs<T> a) {
+    using U = typename Tr<T>::U;
+    const int seg = blockIdx.x, chunk = blockIdx.y, lane = threadIdx.x;
+    const int64_t i0 = (int64_t)seg * a.S;
+    const int64_t i1 = min(i0 + (int64_t)a.S, a.N);
+    const int ns = (int)(i1 - i0);
+    __shared__ U c_ux[WAVE], c_uy[WAVE];
+    __shared__ T c_q[WAVE], c_dz[WAVE];
+    __shared__ cx<T> c_d[MH][WAVE];
+    __shared__ T red[SUB][4][WAVE + 1];
+    __shared__ T outl[SMAX][4];
+    T *outc = a.outk + (int64_t)chunk * a.N * 4;
+    for (int t = lane; t < ns; t += WAVE)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) outl[t][v] = a.accumulate ? outc[(i0 + t) * 4 + v] : (T)0;
+    const int g0 = chunk * a.gpc, g1 = min(g0 + a.gpc, a.ngroups);
+    for (int g = g0; g < g1; ++g) {
+        const int m = g * WAVE + lane;
+        const bool mv = m < a.nmodes;
+        auto cf = [&](int f) -> T { return mv ? a.coef[(int64_t)f * a.cstride + a.moff + m] : (T)0; };
+        const int mx = mv ? a.modes[a.moff + m] : 0;
+        const int my = mv ? a.modes[a.mstride + a.moff + m] : 0;
+        const T kx = cf(0), ky = cf(1), k = cf(2), om = cf(3), ak = cf(4), akd = cf(5);
+        T alr[MH], ali[MH], adr[MH], adi[MH], ndr[MH], ndi[MH];
+#pragma unroll
+        for (int l = 0; l < MH; ++l) {
+            alr[l] = cf(6 + 4 * l);
+            ali[l] = cf(7 + 4 * l);
+            adr[l] = cf(8 + 4 * l);
+            adi[l] = cf(9 + 4 * l);
+            ndr[l] = -adr[l];
+            ndi[l] = -adi[l];
+        }
+        sweep_dir<T, MH, 0>(a, seg, m, i0, i1, mx, my, kx, ky, k, om, ak, akd, alr, ali, adr, adi,
+                            c_ux, c_uy, c_q, c_dz, c_d, red, outl);
+        sweep_dir<T, MH, 1>(a, seg, m, i0, i1, mx, my, kx, ky, k, om, ak, -akd, alr, ali, ndr,
+                            ndi, c_ux, c_uy, c_q, c_dz, c_d, red, outl);
+    }
+    __syncthreads();
+    for (int t = lane; t < ns; t += WAVE)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) outc[(i0 + t) * 4 + v] = outl[t][v];
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: FP64 scan of the aggregates over segments -> carries (in place)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct CArgs {
+    int nseg, ncols, S, mh, gpad, nmodes;
+    int64_t N;
+    const T *z;
+    const cx<double> *spans;  // [nseg][mh][2]: W (inside), G (gap above)
+    cx<T> *agg;               // [2][nseg][ncols]
+    const T *coef;
+    int64_t cstride, moff;
+};
+
+constexpr int CAR_COLS = 16;
+constexpr int CAR_RANGES = 64;
+
+// KMODE: the last slot is beta = k of the column's mode; otherwise beta = 0.
+template <typename T, bool KMODE>
+__global__ __launch_bounds__(CAR_COLS *CAR_RANGES) void k_carry(const CArgs<T> a) {
+    __shared__ cx<double> sc[CAR_RANGES][CAR_COLS], sd[CAR_RANGES][CAR_COLS];
+    const int tc = threadIdx.x % CAR_COLS, r = threadIdx.x / CAR_COLS;
+    const int col = blockIdx.x * CAR_COLS + tc;
+    const bool cv = col < a.ncols;
+    const int slot = cv ? col / (2 * a.gpad) : 0;
+    const int mode = cv ? col % a.gpad : 0;
+    const bool pair = slot < a.mh;
+    double kk = 0.0;
+    if (KMODE && cv && !pair && mode < a.nmodes) kk = (double)a.coef[2 * a.cstride + a.moff + mode];
+    const int L = (a.nseg + CAR_RANGES - 1) / CAR_RANGES;
+    const int s0 = min(r * L, a.nseg), s1 = min(s0 + L, a.nseg);
+    auto WG = [&](int s, cx<double> &W, cx<double> &G) {
+        if (pair) {
+            W = a.spans[((int64_t)s * a.mh + slot) * 2];
+            G = a.spans[((int64_t)s * a.mh + slot) * 2 + 1];
+        } else if (KMODE) {
+            const int64_t b = (int64_t)s * a.S, e = min(b + (int64_t)a.S, a.N) - 1;
+            const double zf = (double)a.z[b], zl = (double)a.z[e];
+            const double zn = (s + 1 < a.nseg) ? (double)a.z[(int64_t)(s + 1) * a.S] : zl;
+            W = cx<double>{exp(-kk * (zl - zf)), 0.0};
+            G = cx<double>{exp(-kk * (zn - zl)), 0.0};
+        } else {
+            W = cx<double>{1.0, 0.0};
+            G = cx<double>{1.0, 0.0};
+        }
+    };
+    cx<T> *AF = a.agg;
+    cx<T> *AB = a.agg + (int64_t)a.nseg * a.ncols;
+    // ---------------- forward: CF_{s+1} = G_s (AF_s + W_s CF_s) ----------------
+    cx<double> c{0.0, 0.0}, D{1.0, 0.0};
+    if (cv)
+        for (int s = s0; s < s1; ++s) {
+            cx<double> W, G;
+            WG(s, W, G);
+            const cx<T> av = AF[(int64_t)s * a.ncols + col];
+            cx<double> t = cmul(W, c);
+            t.re += (double)av.re;
+            t.im += (double)av.im;
+            c = cmul(G, t);
+            D = cmul(G, cmul(W, D));
+        }
+    sc[r][tc] = c;
+    sd[r][tc] = D;
+    __syncthreads();
+    if (r == 0) {
+        cx<double> carry{0.0, 0.0};
+        for (int rr = 0; rr < CAR_RANGES; ++rr) {
+            const cx<double> cc = sc[rr][tc], dd = sd[rr][tc];
+            sc[rr][tc] = carry;
+            const cx<double> t = cmul(dd, carry);
+            carry = cx<double>{cc.re + t.re, cc.im + t.im};
+        }
+    }
+    __syncthreads();
+    c = sc[r][tc];
+    if (cv)
+        for (int s = s0; s < s1; ++s) {
+            cx<double> W, G;
+            WG(s, W, G);
+            const int64_t ix = (int64_t)s * a.ncols + col;
+            const cx<T> av = AF[ix];
+            AF[ix] = cx<T>{(T)c.re, (T)c.im};
+            cx<double> t = cmul(W, c);
+            t.re += (double)av.re;
+            t.im += (double)av.im;
+            c = cmul(G, t);
+        }
+    __syncthreads();
+    // ---------------- backward: CB_{s-1} = G_{s-1} (AB_s + W_s CB_s) ----------------
+    c = cx<double>{0.0, 0.0};
+    D = cx<double>{1.0, 0.0};
+    if (cv)
+        for (int s = s1 - 1; s >= s0; --s) {
+            cx<double> W, G, Wm, Gm{0.0, 0.0};
+            WG(s, W, G);
+            if (s > 0) WG(s - 1, Wm, Gm);
+            const cx<T> av = AB[(int64_t)s * a.ncols + col];
+            cx<double> t = cmul(W, c);
+            t.re += (double)av.re;
+            t.im += (double)av.im;
+            c = cmul(Gm, t);
+            D = cmul(Gm, cmul(W, D));
+        }
+    sc[r][tc] = c;
+    sd[r][tc] = D;
+    __syncthreads();
+    if (r == 0) {
+        cx<double> carry{0.0, 0.0};
+        for (int rr = CAR_RANGES - 1; rr >= 0; --rr) {
+            const cx<double> cc = sc[rr][tc], dd = sd[rr][tc];
+            sc[rr][tc] = carry;
+            const cx<double> t = cmul(dd, carry);
+            carry = cx<double>{cc.re + t.re, cc.im + t.im};
+        }
+    }
+    __syncthreads();
+    c = sc[r][tc];
+    if (cv)
+        for (int s = s1 - 1; s >= s0; --s) {
+            cx<double> W, G, Wm, Gm{0.0, 0.0};
+            WG(s, W, G);
+            if (s > 0) WG(s - 1, Wm, Gm);
+            const int64_t ix = (int64_t)s * a.ncols + col;
+            const cx<T> av = AB[ix];
+            AB[ix] = cx<T>{(T)c.re, (T)c.im};
+            cx<double> t = cmul(W, c);
+            t.re += (double)av.re;
+            t.im += (double)av.im;
+            c = cmul(Gm, t);
+        }
+}
+
+// per (segment, pair): W = e^{-beta (z_last - z_first)}, G = e^{-beta (z_next_first - z_last)}
+template <typename T>
+__global__ __launch_bounds__(256) void k_spans(const T *__restrict__ z, int64_t N, int S, int nseg,
+                                               PairParams pp, cx<double> *__restrict__ spans) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nseg * pp.mh) return;
+    const int s = (int)(idx / pp.mh), l = (int)(idx % pp.mh);
+    const int64_t b = (int64_t)s * S, e = min(b + (int64_t)S, N) - 1;
+    const double zf = (double)z[b], zl = (double)z[e];
+    const double zn = (s + 1 < nseg) ? (double)z[(int64_t)(s + 1) * S] : zl;
+    const double br = pp.beta_re[l], bi = pp.beta_im[l];
+    double sn, cs;
+    sincos(bi * (zl - zf), &sn, &cs);
+    double m = exp(-br * (zl - zf));
+    spans[idx * 2] = cx<double>{m * cs, -m * sn};
+    sincos(bi * (zn - zl), &sn, &cs);
+    m = exp(-br * (zn - zl));
+    spans[idx * 2 + 1] = cx<double>{m * cs, -m * sn};
+}
+
+template <typename T, int MH>
+void launch_passes(Plan *p, const KArgs<T> &ka, int nchunks_b, dim3 grid) {
+    k_agg<T, MH><<<grid, WAVE, 0, p->stream>>>(ka);
+}
+
+template <typename T, int MH>
+void launch_sweep(Plan *p, const KArgs<T> &ka, dim3 grid) {
+    k_sweep<T, MH><<<grid, WAVE, 0, p->stream>>>(ka);
+}
+
+template <typename T>
+void dispatch_agg(Plan *p, const KArgs<T> &ka, dim3 grid) {
+    switch (p->mh) {
+#define Q2D_CASE(n)                                              \
+    case n:                                                      \
+        k_agg<T, n><<<grid, WAVE, 0, p->stream>>>(ka);           \
+        break;
+        Q2D_CASE(1) Q2D_CASE(2) Q2D_CASE(3) Q2D_CASE(4) Q2D_CASE(5) Q2D_CASE(6) Q2D_CASE(7)
+        Q2D_CASE(8) Q2D_CASE(9) Q2D_CASE(10) Q2D_CASE(11) Q2D_CASE(12) Q2D_CASE(13)
+        Q2D_CASE(14) Q2D_CASE(15) Q2D_CASE(16)
+#undef Q2D_CASE
+        default:
+            break;
+    }
+}
+
+template <typename T>
+void dispatch_sweep(Plan *p, const KArgs<T> &ka, dim3 grid) {
+    switch (p->mh) {
+#define Q2D_CASE(n)                                              \
+    case n:                                                      \
+        k_sweep<T, n><<<grid, WAVE, 0, p->stream>>>(ka);         \
+        break;
+        Q2D_CASE(1) Q2D_CASE(2) Q2D_CASE(3) Q2D_CASE(4) Q2D_CASE(5) Q2D_CASE(6) Q2D_CASE(7)
+        Q2D_CASE(8) Q2D_CASE(9) Q2D_CASE(10) Q2D_CASE(11) Q2D_CASE(12) Q2D_CASE(13)
+        Q2D_CASE(14) Q2D_CASE(15) Q2D_CASE(16)
+#undef Q2D_CASE
+        default:
+            break;
+    }
+}
+
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return (v && *v) ? atoi(v) : dflt;
+}
+
+// segment length: multiple of 64, at most SMAX, aiming at ~2048 segments
+int choose_S(int64_t N) {
+    int s = env_int("Q2D_SEG", 0);
+    if (s <= 0) {
+        const int64_t want = (N + 2047) / 2048;
+        s = (int)(((want + WAVE - 1) / WAVE) * WAVE);
+    }
+    s = ((s + WAVE - 1) / WAVE) * WAVE;
+    if (s < WAVE) s = WAVE;
+    if (s > SMAX) s = SMAX;
+    return s;
+}
+
+template <typename T>
+q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coef,
+                       int64_t cstride, int64_t moff0, int64_t nmodes, bool accumulate,
+                       int *nchunks_out) {
+    using U = typename Tr<T>::U;
+    *nchunks_out = 0;
+    if (nmodes <= 0 || N <= 0) return Q2D_OK;
+    const int S = choose_S(N);
+    const int nseg = (int)((N + S - 1) / S);
+    const int mh = p->mh;
+    q2d_status st;
+    if ((st = ensure(p, p->spans, (size_t)nseg * mh * 2 * sizeof(cx<double>))) != Q2D_OK) return st;
+    {
+        const int64_t n = (int64_t)nseg * mh;
+        k_spans<T><<<(int)((n + 255) / 256), 256, 0, p->stream>>>((const T *)p->s_z.p, N, S, nseg,
+                                                                   p->pp, (cx<double> *)p->spans.p);
+    }
+    const int64_t MB = env_int("Q2D_MODE_BATCH", 1024);
+    const int64_t nb0 = nmodes < MB ? nmodes : MB;
+    const int ngroups0 = (int)((nb0 + WAVE - 1) / WAVE);
+    // groups per chunk: enough waves to fill the chip, few partial buffers
+    int gpc = env_int("Q2D_GPC", 0);
+    if (gpc <= 0) {
+        const int target = 2048;
+        int nch = (target + nseg - 1) / nseg;
+        if (nch > ngroups0) nch = ngroups0;
+        if (nch < 1) nch = 1;
+        gpc = (ngroups0 + nch - 1) / nch;
+    }
+    const int nchunks = (ngroups0 + gpc - 1) / gpc;
+    const int gpad0 = ngroups0 * WAVE;
+    const size_t aggsz = (size_t)2 * nseg * (mh + 1) * 2 * gpad0 * sizeof(cx<T>);
+    if ((st = ensure(p, p->agg, aggsz)) != Q2D_OK) return st;
+    if ((st = ensure(p, p->outk, (size_t)nchunks * N * 4 * sizeof(T))) != Q2D_OK) return st;
+
+    KArgs<T> ka{};
+    ka.N = N;
+    ka.S = S;
+    ka.nseg = nseg;
+    ka.ux = (const U *)p->s_ux.p;
+    ka.uy = (const U *)p->s_uy.p;
+    ka.z = (const T *)p->s_z.p;
+    ka.q = (const T *)p->s_q.p;
+    ka.modes = modes;
+    ka.mstride = cstride;
+    ka.coef = (const T *)coef;
+    ka.cstride = cstride;
+    ka.gpc = gpc;
+    for (int l = 0; l < mh; ++l) {
+        ka.bre[l] = (T)p->pp.beta_re[l];
+        ka.bim[l] = (T)p->pp.beta_im[l];
+    }
+    ka.agg = (cx<T> *)p->agg.p;
+    ka.outk = (T *)p->outk.p;
+    for (int64_t b0 = 0; b0 < nmodes; b0 += MB) {
+        const int64_t nb = (nmodes - b0) < MB ? (nmodes - b0) : MB;
+        const int ngroups = (int)((nb + WAVE - 1) / WAVE);
+        const int nchunks_b = (ngroups + gpc - 1) / gpc;
+        ka.moff = moff0 + b0;
+        ka.nmodes = (int)nb;
+        ka.ngroups = ngroups;
+        ka.gpad = ngroups * WAVE;
+        ka.accumulate = (accumulate || b0 > 0) ? 1 : 0;
+        const dim3 grid(nseg, nchunks_b);
+        tstart(p, 1);
+        dispatch_agg<T>(p, ka, grid);
+        tstop(p, 1);
+        CArgs<T> ca{};
+        ca.nseg = nseg;
+        ca.ncols = (mh + 1) * 2 * ka.gpad;
+        ca.S = S;
+        ca.mh = mh;
+        ca.gpad = ka.gpad;
+        ca.nmodes = (int)nb;
+        ca.N = N;
+        ca.z = ka.z;
+        ca.spans = (const cx<double> *)p->spans.p;
+        ca.agg = ka.agg;
+        ca.coef = ka.coef;
+        ca.cstride = cstride;
+        ca.moff = ka.moff;
+        k_carry<T, true><<<(ca.ncols + CAR_COLS - 1) / CAR_COLS, CAR_COLS * CAR_RANGES, 0,
+                           p->stream>>>(ca);
+        tstart(p, 0);
+        dispatch_sweep<T>(p, ka, grid);
+        tstop(p, 0);
+    }
+    *nchunks_out = nchunks;
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+}  // namespace
+
+q2d_status kmodes_run(Plan *p, int64_t N, const int32_t *modes, const void *coef,
+                      int64_t coef_stride, int64_t mode_off, int64_t n_modes, bool accumulate,
+                      int *n_chunks_out) {
+    return p->fp32 ? kmodes_impl<float>(p, N, modes, coef, coef_stride, mode_off, n_modes,
+                                        accumulate, n_chunks_out)
+                   : kmodes_impl<double>(p, N, modes, coef, coef_stride, mode_off, n_modes,
+                                         accumulate, n_chunks_out);
+}
+
+// exported for the k = 0 pass (same carry algebra, beta = 0 last slot)
+q2d_status carry_k0(Plan *p, int nseg, int S, int64_t N) {
+    CArgs<double> ca{};
+    ca.nseg = nseg;
+    ca.ncols = (p->mh + 1) * 2;
+    ca.S = S;
+    ca.mh = p->mh;
+    ca.gpad = 1;
+    ca.nmodes = 0;
+    ca.N = N;
+    ca.z = nullptr;
+    ca.spans = (const cx<double> *)p->spans0.p;
+    ca.agg = (cx<double> *)p->agg0.p;
+    ca.coef = nullptr;
+    k_carry<double, false><<<(ca.ncols + CAR_COLS - 1) / CAR_COLS, CAR_COLS * CAR_RANGES, 0,
+                             p->stream>>>(ca);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+// spans for the k = 0 segmentation (z in the plan's precision)
+q2d_status spans_k0(Plan *p, int nseg, int S, int64_t N) {
+    const int64_t n = (int64_t)nseg * p->mh;
+    if (n == 0) return Q2D_OK;
+    if (p->fp32)
+        k_spans<float><<<(int)((n + 255) / 256), 256, 0, p->stream>>>(
+            (const float *)p->s_z.p, N, S, nseg, p->pp, (cx<double> *)p->spans0.p);
+    else
+        k_spans<double><<<(int)((n + 255) / 256), 256, 0, p->stream>>>(
+            (const double *)p->s_z.p, N, S, nseg, p->pp, (cx<double> *)p->spans0.p);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+}  // namespace q2d

@@ -1,0 +1,277 @@
+// Stable z-sort of the particles and staging of the sorted structure-of-arrays.
+//
+// The recursion of Sec. 3.2 needs the particles ordered by height z (i > j
+// <=> z_i >= z_j) so that every exponent in the scans is non-positive (the
+// stability remark after eq. 35).  Sort keys are the IEEE bit patterns of z:
+// for z >= 0 they order like the numbers (z + 0 turns -0 into +0).  The sort
+// is a least-significant-digit radix sort with 8-bit digits; each pass is
+// stable, so equal heights keep input order.
+//
+// One pass = (1) per-tile digit histograms, (2) per-digit exclusive scan over
+// tiles, (3) a stable scatter that ranks keys inside a tile with wave ballots.
+#include "q2d_internal.h"
+
+namespace q2d {
+
+namespace {
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 8;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
+
+__device__ inline uint32_t zkey(float z) { return __float_as_uint(z + 0.0f); }
+__device__ inline uint64_t zkey(double z) {
+    return static_cast<uint64_t>(__double_as_longlong(z + 0.0));
+}
+
+// Status bits in the device status word (bit q2d_status).
+__device__ inline void set_status(int *st, int code) { atomicOr(st, 1 << code); }
+
+template <typename T, typename K>
+__global__ __launch_bounds__(256) void k_stage(const T *__restrict__ pos, const T *__restrict__ q,
+                                               int64_t N, K *__restrict__ keys,
+                                               int32_t *__restrict__ vals, double Lz,
+                                               int validate, int *status, double *qsums) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double qv = 0.0;
+    if (i < N) {
+        const T z = pos[3 * i + 2];
+        keys[i] = zkey(z);
+        vals[i] = (int32_t)i;
+        if (validate) {
+            const T x = pos[3 * i], y = pos[3 * i + 1];
+            qv = (double)q[i];
+            const bool finite = isfinite((double)x) && isfinite((double)y) &&
+                                isfinite((double)z) && isfinite(qv);
+            if (!finite || !((double)z >= 0.0 && (double)z <= Lz)) set_status(status, Q2D_EOUTOFBOX);
+        }
+    }
+    if (validate) {
+        // block sums of q and |q| for the neutrality check (order of the final
+        // atomic adds only affects a threshold test)
+        __shared__ double s1[256], s2[256];
+        s1[threadIdx.x] = qv;
+        s2[threadIdx.x] = fabs(qv);
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) {
+                s1[threadIdx.x] += s1[threadIdx.x + h];
+                s2[threadIdx.x] += s2[threadIdx.x + h];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            atomicAdd(&qsums[0], s1[0]);
+            atomicAdd(&qsums[1], s2[0]);
+        }
+    }
+}
+
+__global__ void k_neutral_check(const double *qsums, int *status) {
+    if (fabs(qsums[0]) > 1e-6 * qsums[1] + 1e-300) atomicOr(status, 1 << Q2D_ENONNEUTRAL);
+}
+
+__global__ void k_zero2(double *a) {
+    a[0] = 0.0;
+    a[1] = 0.0;
+}
+
+template <typename K>
+__global__ __launch_bounds__(SORT_THREADS) void k_hist(const K *__restrict__ keys, int64_t N,
+                                                       int shift, uint32_t *__restrict__ hist,
+                                                       int ntiles) {
+    __shared__ uint32_t h[256];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int64_t i = base + r * SORT_THREADS + t;
+        if (i < N) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)t * ntiles + blockIdx.x] = h[t];
+}
+
+// One block per digit: exclusive scan of hist[d][*] over tiles, total in tot[d].
+__global__ __launch_bounds__(256) void k_scan_digit(uint32_t *__restrict__ hist, int ntiles,
+                                                    uint32_t *__restrict__ tot) {
+    __shared__ uint32_t part[256];
+    const int d = blockIdx.x, t = threadIdx.x;
+    uint32_t *row = hist + (int64_t)d * ntiles;
+    const int per = (ntiles + 255) / 256;
+    const int b0 = min(t * per, ntiles), b1 = min(b0 + per, ntiles);
+    uint32_t s = 0;
+    for (int b = b0; b < b1; ++b) s += row[b];
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 256 partial sums
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t v = (t >= off) ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = (t > 0) ? part[t - 1] : 0u;
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t c = row[b];
+        row[b] = run;
+        run += c;
+    }
+    if (t == 255) tot[d] = part[255];
+}
+
+template <typename K>
+__global__ __launch_bounds__(SORT_THREADS) void k_scatter(
+    const K *__restrict__ kin, const int32_t *__restrict__ vin, K *__restrict__ kout,
+    int32_t *__restrict__ vout, int64_t N, int shift, const uint32_t *__restrict__ hist,
+    const uint32_t *__restrict__ tot, int ntiles) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[SORT_THREADS / WAVE][256];
+    const int t = threadIdx.x;
+    const int wave = t / WAVE, lane = t % WAVE;
+    // digit base = (keys with smaller digits) + (same digit in earlier tiles)
+    base[t] = tot[t];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t v = (t >= off) ? base[t - off] : 0u;
+        __syncthreads();
+        base[t] += v;
+        __syncthreads();
+    }
+    const uint32_t excl = base[t] - tot[t];
+    __syncthreads();
+    base[t] = excl + hist[(int64_t)t * ntiles + blockIdx.x];
+    run[t] = 0;
+#pragma unroll
+    for (int w = 0; w < SORT_THREADS / WAVE; ++w) wc[w][t] = 0;
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t tile0 = (int64_t)blockIdx.x * SORT_TILE;
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int64_t i = tile0 + r * SORT_THREADS + t;
+        const bool valid = i < N;
+        const K k = valid ? kin[i] : (K)0;
+        const int32_t v = valid ? vin[i] : 0;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        if (valid && rank == 0) wc[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = base[d] + run[d] + rank;
+            for (int w = 0; w < wave; ++w) off += wc[w][d];
+            kout[off] = k;
+            vout[off] = v;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < SORT_THREADS / WAVE; ++w) {
+            add += wc[w][t];
+            wc[w][t] = 0;
+        }
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+struct Fix;
+template <>
+struct Fix<float> {
+    using U = uint32_t;
+    __device__ static U frac(double v) {
+        // fixed-point fraction of a turn: round(frac(v) * 2^32) mod 2^32
+        double f = v - floor(v);
+        return (U)(uint64_t)llrint(f * 4294967296.0);
+    }
+};
+template <>
+struct Fix<double> {
+    using U = double;
+    __device__ static U frac(double v) { return v - floor(v); }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(const T *__restrict__ pos,
+                                                const T *__restrict__ q,
+                                                const int32_t *__restrict__ perm, int64_t N,
+                                                double Lx, double Ly,
+                                                typename Fix<T>::U *__restrict__ ux,
+                                                typename Fix<T>::U *__restrict__ uy,
+                                                T *__restrict__ zs, T *__restrict__ qs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int64_t o = perm[i];
+    ux[i] = Fix<T>::frac((double)pos[3 * o] / Lx);
+    uy[i] = Fix<T>::frac((double)pos[3 * o + 1] / Ly);
+    zs[i] = pos[3 * o + 2] + (T)0;
+    qs[i] = q[o];
+}
+
+template <typename T, typename K>
+q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
+    const T *pos = (const T *)pos_v;
+    const T *q = (const T *)q_v;
+    using U = typename Fix<T>::U;
+    q2d_status st;
+    if ((st = ensure(p, p->keys_a, N * sizeof(K))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->keys_b, N * sizeof(K))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->vals_a, N * sizeof(int32_t))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->vals_b, N * sizeof(int32_t))) != Q2D_OK) return st;
+    const int ntiles = (int)((N + SORT_TILE - 1) / SORT_TILE);
+    if ((st = ensure(p, p->hist, ((size_t)256 * ntiles + 256) * sizeof(uint32_t))) != Q2D_OK)
+        return st;
+    if ((st = ensure(p, p->s_ux, N * sizeof(U))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->s_uy, N * sizeof(U))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->s_z, N * sizeof(T))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->s_q, N * sizeof(T))) != Q2D_OK) return st;
+
+    int *status = (int *)p->status.p;
+    double *qsums = (double *)((char *)p->status.p + 16);
+    const int nb = (int)((N + 255) / 256);
+    if (p->opts.validate) k_zero2<<<1, 1, 0, p->stream>>>(qsums);
+    k_stage<T, K><<<nb, 256, 0, p->stream>>>(pos, q, N, (K *)p->keys_a.p, (int32_t *)p->vals_a.p,
+                                             p->Lz, p->opts.validate, status, qsums);
+    if (p->opts.validate) k_neutral_check<<<1, 1, 0, p->stream>>>(qsums, status);
+
+    uint32_t *hist = (uint32_t *)p->hist.p;
+    uint32_t *tot = hist + (size_t)256 * ntiles;
+    K *kin = (K *)p->keys_a.p, *kout = (K *)p->keys_b.p;
+    int32_t *vin = (int32_t *)p->vals_a.p, *vout = (int32_t *)p->vals_b.p;
+    const int passes = (int)sizeof(K);
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        k_hist<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, N, shift, hist, ntiles);
+        k_scan_digit<<<256, 256, 0, p->stream>>>(hist, ntiles, tot);
+        k_scatter<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, vin, kout, vout, N, shift, hist,
+                                                            tot, ntiles);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    p->perm = vin;
+    k_gather<T><<<nb, 256, 0, p->stream>>>(pos, q, p->perm, N, p->Lx, p->Ly, (U *)p->s_ux.p,
+                                           (U *)p->s_uy.p, (T *)p->s_z.p, (T *)p->s_q.p);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+}  // namespace
+
+q2d_status sort_and_stage(Plan *p, const void *pos, const void *q, int64_t N) {
+    tstart(p, 2);
+    q2d_status st = p->fp32 ? sort_impl<float, uint32_t>(p, pos, q, N)
+                            : sort_impl<double, uint64_t>(p, pos, q, N);
+    tstop(p, 2);
+    return st;
+}
+
+}  // namespace q2d

@@ -1,0 +1,166 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: FP64 results within 1e-10 relative (norm over all particles) of the
+FP64 oracle on the same SOE table and modes; FP32 results within 1e-5 at these
+sizes (1e-4 is the stated bar for the FP32 force at N = 1e6); sampled modes and
+the sort's integer work bit-exact.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2403_01521_amd as q2d  # noqa: E402
+import workloads as wl  # noqa: E402
+from oracle import lattice, rbsampler, soewald2d  # noqa: E402
+from oracle import recursion as o3  # noqa: E402
+
+
+def dev(a, dt):
+    return torch.tensor(np.asarray(a), dtype=dt, device="cuda")
+
+
+def rel(a, b):
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_exact(c, w, s, prec, pos=None, q=None):
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    pos = c["pos"] if pos is None else pos
+    q = c["q"] if q is None else q
+    plan = q2d.Plan(c["box"], c["alpha"], w, s, kc=c["kc"], precision=prec, n_max=max(1, len(q)))
+    phi, F, E = plan.long_range(dev(pos, dt), dev(q, dt))
+    torch.cuda.synchronize()
+    out = phi.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), float(E.cpu()[0])
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_exact_k_config1(soe_tables, prec, tol):
+    c = wl.make_config(1, dtype=np.float32 if prec == "fp32" else np.float64)
+    w, s = soe_tables[16]
+    phi, F, E = run_exact(c, w, s, prec)
+    r = soewald2d.exact_k(c["pos"], c["q"], c["box"], c["alpha"], c["kc"], w, s)
+    print("config1", prec, rel(phi, r["phi"]), rel(F, r["F"]), abs(E - r["U"]) / abs(r["U"]))
+    assert rel(phi, r["phi"]) < tol
+    assert rel(F, r["F"]) < tol
+    assert abs(E - r["U"]) < tol * abs(r["U"])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_exact_k_config2(soe_tables, prec, tol):
+    c = wl.make_config(2, dtype=np.float32 if prec == "fp32" else np.float64)
+    w, s = soe_tables[24]
+    phi, F, E = run_exact(c, w, s, prec)
+    m, wt = soewald2d.exact_modes(c["box"][0], c["box"][1], c["alpha"], c["kc"])
+    r = o3.long_range(c["pos"], c["q"], c["box"], c["alpha"], w, s, m, wt, nthreads=8)
+    print("config2", prec, len(m), rel(phi, r["phi"]), rel(F, r["F"]), abs(E - r["U"]) / abs(r["U"]))
+    assert rel(phi, r["phi"]) < tol
+    assert rel(F, r["F"]) < tol
+    assert abs(E - r["U"]) < tol * abs(r["U"])
+    # direct pair sums on sampled targets
+    tg = np.random.default_rng(0).choice(len(c["q"]), 8, replace=False)
+    r2 = soewald2d.exact_k(c["pos"], c["q"], c["box"], c["alpha"], c["kc"], w, s, targets=tg)
+    assert rel(phi[tg], r2["phi"]) < tol
+    assert rel(F[tg], r2["F"]) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_rbm_step_matches_oracle(soe_tables, prec, tol):
+    dtn = np.float32 if prec == "fp32" else np.float64
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    c = wl.make_config(3, dtype=dtn, n_override=20000)
+    w, s = soe_tables[16]
+    box, alpha = c["box"], c["alpha"]
+    P = 100
+    plan = q2d.Plan(box, alpha, w, s, precision=prec, n_max=len(c["q"]), p_max=P)
+    phi, F, E, modes = plan.rbm_step(dev(c["pos"], dt), dev(c["q"], dt), P, seed=7, step=3)
+    torch.cuda.synchronize()
+    phi = phi.cpu().numpy().astype(np.float64)
+    F = F.cpu().numpy().astype(np.float64)
+    E = float(E.cpu()[0])
+    modes = modes.cpu().numpy()
+    ref_modes, _ = rbsampler.sample_modes(7, 3, P, alpha, box[0], box[1])
+    assert np.array_equal(modes, ref_modes)
+    info = plan.info()
+    H = lattice.H_direct(box[0], box[1], alpha)
+    assert abs(info["H"] - H) < 1e-12 * H
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    assert abs(info["diag_rb"] - D) < 1e-12 * abs(D)
+    r = o3.long_range(c["pos"], c["q"], box, alpha, w, s, modes,
+                      soewald2d.rb_weights(P, H, box[0], box[1]), include_self_pair=False,
+                      diag=D, nthreads=8)
+    print("rbm", prec, rel(phi, r["phi"]), rel(F, r["F"]), abs(E - r["U"]) / abs(r["U"]))
+    assert rel(phi, r["phi"]) < tol
+    assert rel(F, r["F"]) < tol
+    assert abs(E - r["U"]) < tol * abs(r["U"])
+    plan.close()
+
+
+def test_empty_and_single(soe_tables):
+    w, s = soe_tables[16]
+    box = (10.0, 10.0, 4.0)
+    plan = q2d.Plan(box, 0.5, w, s, kc=3.0, precision="fp64", n_max=8, p_max=4)
+    pos = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    q = torch.zeros(0, dtype=torch.float64, device="cuda")
+    phi, F, E = plan.long_range(pos, q)
+    assert float(E.cpu()[0]) == 0.0
+    phi, F, E, m = plan.rbm_step(pos, q, 4, 1, 1)
+    assert float(E.cpu()[0]) == 0.0
+    # one neutral "particle" (q = 0): everything vanishes
+    p1 = torch.tensor([[1.0, 2.0, 3.0]], dtype=torch.float64, device="cuda")
+    q1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    phi, F, E = plan.long_range(p1, q1)
+    assert float(phi.abs().max()) == 0.0 and float(F.abs().max()) == 0.0
+    with pytest.raises(q2d.Q2DError):
+        plan.long_range(torch.zeros((9, 3), dtype=torch.float64, device="cuda"),
+                        torch.zeros(9, dtype=torch.float64, device="cuda"))
+    with pytest.raises(q2d.Q2DError):
+        plan.rbm_step(p1, q1, 5, 1, 1)
+    plan.close()
+
+
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 1000, 4097])
+def test_ragged_sizes_fp64(soe_tables, n):
+    w, s = soe_tables[12]
+    box = (12.0, 9.0, 3.0)
+    pos, q = wl.random_system(n, box, seed=100 + n)
+    c = dict(box=box, alpha=0.6, kc=3.5)
+    phi, F, E = run_exact(c, w, s, "fp64", pos=pos, q=q)
+    m, wt = soewald2d.exact_modes(box[0], box[1], 0.6, 3.5)
+    r = o3.long_range(pos, q, box, 0.6, w, s, m, wt, nthreads=8)
+    print("ragged", n, rel(phi, r["phi"]), rel(F, r["F"]))
+    assert rel(phi, r["phi"]) < 1e-10
+    assert rel(F, r["F"]) < 1e-10
+
+
+def test_equal_heights_square_lattice(soe_tables):
+    """All ions in one plane (sort ties): the square ionic lattice."""
+    w, s = soe_tables[24]
+    a = 1.0
+    cell, qc = wl.square_ionic_cell(a, 0.5)
+    # 8 x 8 copies of the cell in a 16 x 16 box
+    pos = np.concatenate([cell + [2 * a * i, 2 * a * j, 0] for i in range(8) for j in range(8)])
+    q = np.tile(qc, 64)
+    box = (16.0, 16.0, 1.0)
+    c = dict(box=box, alpha=1.2, kc=1.2 * 12)
+    phi, F, E = run_exact(c, w, s, "fp64", pos=pos, q=q)
+    r = soewald2d.exact_k(pos, q, box, 1.2, 1.2 * 12, w, s, targets=np.arange(4))
+    assert rel(phi[:4], r["phi"]) < 1e-10
+    assert np.abs(F).max() < 1e-9
+
+
+def test_deterministic(soe_tables):
+    w, s = soe_tables[16]
+    c = wl.make_config(3, dtype=np.float32, n_override=30000)
+    plan = q2d.Plan(c["box"], c["alpha"], w, s, precision="fp32", n_max=30000, p_max=100)
+    pos, q = dev(c["pos"], torch.float32), dev(c["q"], torch.float32)
+    a = [t.clone() for t in plan.rbm_step(pos, q, 100, 5, 9)]
+    b = [t.clone() for t in plan.rbm_step(pos, q, 100, 5, 9)]
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    plan.close()

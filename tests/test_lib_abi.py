@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports every symbol include/q2d.h declares;
+host-only entry points work without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2403_01521_amd as q2d
+from oracle import soe as osoe
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "q2d.h")
+
+
+def declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(q2d_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(q2d.EXPORTS) == declared()
+
+
+def test_library_exports_every_symbol():
+    lib = q2d.load_library()
+    for name in declared():
+        assert hasattr(lib, name), name
+    out = os.popen("nm -D --defined-only %s" % q2d.LIB_PATH).read()
+    for name in declared():
+        assert re.search(r" T %s$" % name, out, re.M), name
+
+
+def test_status_strings():
+    lib = q2d.load_library()
+    for code in range(9):
+        assert lib.q2d_status_string(code)
+    assert lib.q2d_status_string(0) == b"ok"
+
+
+@pytest.mark.parametrize("M", [8, 16, 24])
+def test_host_soe_fit(M):
+    w, s, err = q2d.soe_fit(M)
+    assert len(w) == M
+    bound = {8: 4e-5, 16: 1e-9, 24: 5e-14}[M]
+    assert err < bound
+    # independent check with the oracle's evaluator
+    x = np.linspace(0, 8, 20001)
+    assert np.abs(osoe.soe_eval(w, s, x) - np.exp(-x * x)).max() < bound
+    assert np.all(s.real > 0)
+    assert abs(np.sum(w) - 1) < bound
+
+
+def test_host_argument_checks():
+    lib = q2d.load_library()
+    w, s, _ = q2d.soe_fit(8)
+    wi = np.empty(16); wi[0::2], wi[1::2] = w.real, w.imag
+    si = np.empty(16); si[0::2], si[1::2] = s.real, s.imag
+    dp = ctypes.POINTER(ctypes.c_double)
+    h = ctypes.c_void_p()
+    opts = q2d._Opts(0, 1, 100, 0, 0)
+    # odd M, bad box, non-conjugate table, no capacity: all rejected before any device call
+    assert lib.q2d_plan_create(1, 1, 1, 1, 0, 1, 7, wi.ctypes.data_as(dp), si.ctypes.data_as(dp),
+                               ctypes.byref(opts), None, ctypes.byref(h)) == 1
+    assert lib.q2d_plan_create(-1, 1, 1, 1, 0, 1, 8, wi.ctypes.data_as(dp), si.ctypes.data_as(dp),
+                               ctypes.byref(opts), None, ctypes.byref(h)) == 1
+    bad = si.copy(); bad[1] = 0.0
+    assert lib.q2d_plan_create(1, 1, 1, 1, 0, 1, 8, wi.ctypes.data_as(dp), bad.ctypes.data_as(dp),
+                               ctypes.byref(opts), None, ctypes.byref(h)) == 1
+    bad = wi.copy(); bad[1] += 1.0
+    assert lib.q2d_plan_create(1, 1, 1, 1, 0, 1, 8, bad.ctypes.data_as(dp), si.ctypes.data_as(dp),
+                               ctypes.byref(opts), None, ctypes.byref(h)) == 1
+    opts0 = q2d._Opts(0, 1, 0, 0, 0)
+    assert lib.q2d_plan_create(1, 1, 1, 1, 0, 1, 8, wi.ctypes.data_as(dp), si.ctypes.data_as(dp),
+                               ctypes.byref(opts0), None, ctypes.byref(h)) == 1
+    # r_c beyond half the box
+    assert lib.q2d_plan_create(4, 4, 1, 1, 2.5, 1, 8, wi.ctypes.data_as(dp), si.ctypes.data_as(dp),
+                               ctypes.byref(opts), None, ctypes.byref(h)) == 1
+    assert lib.q2d_plan_destroy(None) == 1
