@@ -416,7 +416,7 @@ q2d_status q2d_plan_destroy(q2d_plan_t p) {
     }
     Buf *bufs[] = {&p->exact_modes, &p->exact_coef, &p->rb_modes, &p->rb_coef, &p->rb_work,
                    &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
-                   &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->outk, &p->spans0,
+                   &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->carry_tmp, &p->outk, &p->spans0,
                    &p->agg0, &p->phi0, &p->fz0, &p->epart, &p->status, &p->cell_start,
                    &p->cell_count, &p->cell_idx, &p->cell_tmp};
     for (Buf *b : bufs) free_buf(*b);

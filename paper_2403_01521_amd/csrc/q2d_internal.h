@@ -88,6 +88,7 @@ struct Plan {
     // k != 0 scans
     Buf spans;                 // FP64 complex W,G per (segment, pair)
     Buf agg;                   // aggregates / carries (both directions)
+    Buf carry_tmp;             // per-range transfers of the carry scan
     Buf outk;                  // per-chunk per-particle outputs (T x 4)
 
     // k = 0 scans

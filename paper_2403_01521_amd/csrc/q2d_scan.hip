@@ -44,9 +44,14 @@ struct Tr<double> {
 };
 
 // sin, cos of 2 pi (mx ux + my uy)
+// FP32: the turn count mx ux + my uy is exact modulo 2^32 in fixed point; the
+// hardware sine/cosine take their argument in turns (measured on gfx950:
+// absolute error 1.2e-7 on [-1/2, 1/2)).
 __device__ inline void phase_sc(int mx, int my, uint32_t ux, uint32_t uy, float &s, float &c) {
-    const uint32_t ph = (uint32_t)mx * ux + (uint32_t)my * uy;  // exact modulo one turn
-    sincospif((float)(int32_t)ph * 0x1p-31f, &s, &c);
+    const uint32_t ph = (uint32_t)mx * ux + (uint32_t)my * uy;
+    const float r = (float)(int32_t)ph * 0x1p-32f;  // turns in [-1/2, 1/2)
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
 }
 __device__ inline void phase_sc(int mx, int my, double ux, double uy, double &s, double &c) {
     double r = fma((double)mx, ux, (double)my * uy);
@@ -56,9 +61,15 @@ __device__ inline void phase_sc(int mx, int my, double ux, double uy, double &s,
 
 // exp(-(br + i bi) t)
 __device__ inline cx<float> cexpm(float br, float bi, float t) {
-    const float m = expf(-br * t);
+    const float m = __expf(-br * t);
+    const float turns = bi * t * 0.15915494309189535f;  // 1/(2 pi)
     float s, c;
-    sincosf(bi * t, &s, &c);
+    if (fabsf(turns) < 0.25f) {
+        s = __builtin_amdgcn_sinf(turns);
+        c = __builtin_amdgcn_cosf(turns);
+    } else {
+        sincosf(bi * t, &s, &c);  // large angles (sparse regions): full range reduction
+    }
     return {m * c, -m * s};
 }
 __device__ inline cx<double> cexpm(double br, double bi, double t) {
@@ -68,14 +79,12 @@ __device__ inline cx<double> cexpm(double br, double bi, double t) {
         const double xr = ar, xi = ai;
         double pr = 1.0 / 5040.0, pi = 0.0;
         const double cs[7] = {1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0, 0.5, 1.0, 1.0};
-        const double sg[7] = {1, -1, 1, -1, 1, -1, 1};
         // p(x) = sum_n (-x)^n / n!: Horner in (-x)
 #pragma unroll
         for (int n = 0; n < 7; ++n) {
             const double nr = -(pr * xr - pi * xi), ni = -(pr * xi + pi * xr);
             pr = nr + cs[n];
             pi = ni;
-            (void)sg;
         }
         return {pr, pi};
     }
@@ -195,7 +204,7 @@ __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
 // pass 3: the sweep (recursion) of one segment for the lanes' modes
 // ---------------------------------------------------------------------------
 constexpr int SMAX = 512;  // largest segment
-constexpr int SUB = 16;    // particles per lane-reduction round
+constexpr int SUB = 4;     // particles per lane-reduction round
 
 template <typename T, int MH, int DIR>
 __device__ inline void sweep_dir(const KArgs<T> &a, int seg, int m, int64_t i0, int64_t i1,
@@ -286,11 +295,18 @@ __device__ inline void sweep_dir(const KArgs<T> &a, int seg, int m, int64_t i0, 
             red[r][2][lane] = ky * oq;
             red[r][3][lane] = -om * (c * Xd + s * Yd);
             if (r == SUB - 1 || jj == nb - 1) {
+                // 16 (particle, value) sums of 64 lane contributions: 4 lanes per
+                // sum, 16 entries each (rows padded to 65: conflict-free), then a
+                // quad reduction
                 __syncthreads();
-                const int rj = lane >> 2, v = lane & 3;
-                if (rj <= r) {
-                    T sum = 0;
-                    for (int L = 0; L < WAVE; ++L) sum += red[rj][v][L];
+                const int pv = lane >> 2, part = lane & 3;
+                const int rj = pv >> 2, v = pv & 3;
+                T sum = 0;
+#pragma unroll
+                for (int L = 0; L < WAVE / 4; ++L) sum += red[rj][v][part * (WAVE / 4) + L];
+                sum += __shfl_xor(sum, 1);
+                sum += __shfl_xor(sum, 2);
+                if (part == 0 && rj <= r) {
                     const int pj = jj - r + rj;
                     const int jpart = DIR ? nb - 1 - pj : pj;
                     outl[(int)(ib - i0) + jpart][v] += sum;
@@ -360,24 +376,32 @@ struct CArgs {
     int64_t cstride, moff;
 };
 
-constexpr int CAR_COLS = 16;
-constexpr int CAR_RANGES = 64;
+constexpr int CAR_L = 32;      // segments per range
+constexpr int CAR_BATCH = 4;   // loads issued ahead of the dependent chain
 
-// KMODE: the last slot is beta = k of the column's mode; otherwise beta = 0.
+// Compose two range transfers x -> c + D x: first (c1, D1), then (c2, D2).
+__device__ inline void compose(cx<double> &c2, cx<double> &D2, cx<double> c1, cx<double> D1) {
+    const cx<double> t = cmul(D2, c1);
+    c2 = cx<double>{c2.re + t.re, c2.im + t.im};
+    D2 = cmul(D2, D1);
+}
+
+// Decay factors of segment s for a column: W_s = e^{-beta (z_last - z_first)}
+// inside the segment and G_s = e^{-beta (z_first(s+1) - z_last(s))} across the gap.
 template <typename T, bool KMODE>
-__global__ __launch_bounds__(CAR_COLS *CAR_RANGES) void k_carry(const CArgs<T> a) {
-    __shared__ cx<double> sc[CAR_RANGES][CAR_COLS], sd[CAR_RANGES][CAR_COLS];
-    const int tc = threadIdx.x % CAR_COLS, r = threadIdx.x / CAR_COLS;
-    const int col = blockIdx.x * CAR_COLS + tc;
-    const bool cv = col < a.ncols;
-    const int slot = cv ? col / (2 * a.gpad) : 0;
-    const int mode = cv ? col % a.gpad : 0;
-    const bool pair = slot < a.mh;
-    double kk = 0.0;
-    if (KMODE && cv && !pair && mode < a.nmodes) kk = (double)a.coef[2 * a.cstride + a.moff + mode];
-    const int L = (a.nseg + CAR_RANGES - 1) / CAR_RANGES;
-    const int s0 = min(r * L, a.nseg), s1 = min(s0 + L, a.nseg);
-    auto WG = [&](int s, cx<double> &W, cx<double> &G) {
+struct Decay {
+    const CArgs<T> &a;
+    int slot;
+    bool pair;
+    double kk;
+    __device__ Decay(const CArgs<T> &a_, int col) : a(a_) {
+        slot = col / (2 * a.gpad);
+        const int mode = col % a.gpad;
+        pair = slot < a.mh;
+        kk = 0.0;
+        if (KMODE && !pair && mode < a.nmodes) kk = (double)a.coef[2 * a.cstride + a.moff + mode];
+    }
+    __device__ void get(int s, cx<double> &W, cx<double> &G) const {
         if (pair) {
             W = a.spans[((int64_t)s * a.mh + slot) * 2];
             G = a.spans[((int64_t)s * a.mh + slot) * 2 + 1];
@@ -391,91 +415,156 @@ __global__ __launch_bounds__(CAR_COLS *CAR_RANGES) void k_carry(const CArgs<T> a
             W = cx<double>{1.0, 0.0};
             G = cx<double>{1.0, 0.0};
         }
-    };
-    cx<T> *AF = a.agg;
-    cx<T> *AB = a.agg + (int64_t)a.nseg * a.ncols;
-    // ---------------- forward: CF_{s+1} = G_s (AF_s + W_s CF_s) ----------------
-    cx<double> c{0.0, 0.0}, D{1.0, 0.0};
-    if (cv)
-        for (int s = s0; s < s1; ++s) {
-            cx<double> W, G;
-            WG(s, W, G);
-            const cx<T> av = AF[(int64_t)s * a.ncols + col];
-            cx<double> t = cmul(W, c);
-            t.re += (double)av.re;
-            t.im += (double)av.im;
-            c = cmul(G, t);
-            D = cmul(G, cmul(W, D));
-        }
-    sc[r][tc] = c;
-    sd[r][tc] = D;
-    __syncthreads();
-    if (r == 0) {
-        cx<double> carry{0.0, 0.0};
-        for (int rr = 0; rr < CAR_RANGES; ++rr) {
-            const cx<double> cc = sc[rr][tc], dd = sd[rr][tc];
-            sc[rr][tc] = carry;
-            const cx<double> t = cmul(dd, carry);
-            carry = cx<double>{cc.re + t.re, cc.im + t.im};
+    }
+    // factors of one step in direction dir: forward (W_s, G_s); backward
+    // (W_s, G_{s-1}), the gap below s (none below segment 0)
+    __device__ void step(int dir, int s, cx<double> &W, cx<double> &G) const {
+        get(s, W, G);
+        if (dir) {
+            cx<double> Wm;
+            G = cx<double>{0.0, 0.0};
+            if (s > 0) get(s - 1, Wm, G);
         }
     }
-    __syncthreads();
-    c = sc[r][tc];
-    if (cv)
-        for (int s = s0; s < s1; ++s) {
-            cx<double> W, G;
-            WG(s, W, G);
-            const int64_t ix = (int64_t)s * a.ncols + col;
-            const cx<T> av = AF[ix];
-            AF[ix] = cx<T>{(T)c.re, (T)c.im};
-            cx<double> t = cmul(W, c);
-            t.re += (double)av.re;
-            t.im += (double)av.im;
-            c = cmul(G, t);
+};
+
+// Walk the segments of one range in the direction of propagation starting from
+// carry c: forward CF_{s+1} = G_s (AF_s + W_s CF_s), backward
+// CB_{s-1} = G_{s-1} (AB_s + W_s CB_s).  WRITE: store each segment's carry-in
+// in place of its aggregate.  Returns the carry out and the range's total decay.
+template <typename T, bool KMODE, bool WRITE>
+__device__ inline void walk(const CArgs<T> &a, const Decay<T, KMODE> &dc, int dir, int col,
+                            int s0, int s1, cx<double> &c, cx<double> &D) {
+    cx<T> *AG = a.agg + (dir ? (int64_t)a.nseg * a.ncols : 0);
+    const int n = s1 - s0;
+    for (int k0 = 0; k0 < n; k0 += CAR_BATCH) {
+        cx<T> av[CAR_BATCH];
+        cx<double> W[CAR_BATCH], G[CAR_BATCH];
+#pragma unroll
+        for (int u = 0; u < CAR_BATCH; ++u) {
+            const int k = k0 + u;
+            if (k < n) {
+                const int s = dir ? s1 - 1 - k : s0 + k;
+                dc.step(dir, s, W[u], G[u]);
+                av[u] = AG[(int64_t)s * a.ncols + col];
+            }
         }
-    __syncthreads();
-    // ---------------- backward: CB_{s-1} = G_{s-1} (AB_s + W_s CB_s) ----------------
-    c = cx<double>{0.0, 0.0};
-    D = cx<double>{1.0, 0.0};
-    if (cv)
-        for (int s = s1 - 1; s >= s0; --s) {
-            cx<double> W, G, Wm, Gm{0.0, 0.0};
-            WG(s, W, G);
-            if (s > 0) WG(s - 1, Wm, Gm);
-            const cx<T> av = AB[(int64_t)s * a.ncols + col];
-            cx<double> t = cmul(W, c);
-            t.re += (double)av.re;
-            t.im += (double)av.im;
-            c = cmul(Gm, t);
-            D = cmul(Gm, cmul(W, D));
-        }
-    sc[r][tc] = c;
-    sd[r][tc] = D;
-    __syncthreads();
-    if (r == 0) {
-        cx<double> carry{0.0, 0.0};
-        for (int rr = CAR_RANGES - 1; rr >= 0; --rr) {
-            const cx<double> cc = sc[rr][tc], dd = sd[rr][tc];
-            sc[rr][tc] = carry;
-            const cx<double> t = cmul(dd, carry);
-            carry = cx<double>{cc.re + t.re, cc.im + t.im};
+#pragma unroll
+        for (int u = 0; u < CAR_BATCH; ++u) {
+            const int k = k0 + u;
+            if (k < n) {
+                if (WRITE) {
+                    const int s = dir ? s1 - 1 - k : s0 + k;
+                    AG[(int64_t)s * a.ncols + col] = cx<T>{(T)c.re, (T)c.im};
+                }
+                cx<double> t = cmul(W[u], c);
+                t.re += (double)av[u].re;
+                t.im += (double)av[u].im;
+                c = cmul(G[u], t);
+                if (!WRITE) D = cmul(G[u], cmul(W[u], D));
+            }
         }
     }
-    __syncthreads();
-    c = sc[r][tc];
-    if (cv)
-        for (int s = s1 - 1; s >= s0; --s) {
-            cx<double> W, G, Wm, Gm{0.0, 0.0};
-            WG(s, W, G);
-            if (s > 0) WG(s - 1, Wm, Gm);
-            const int64_t ix = (int64_t)s * a.ncols + col;
-            const cx<T> av = AB[ix];
-            AB[ix] = cx<T>{(T)c.re, (T)c.im};
-            cx<double> t = cmul(W, c);
-            t.re += (double)av.re;
-            t.im += (double)av.im;
-            c = cmul(Gm, t);
+}
+
+// (1) one thread per (column, range): fold the range into x -> c + D x
+template <typename T, bool KMODE>
+__global__ __launch_bounds__(256) void k_cfold(const CArgs<T> a, int nr, cx<double> *rc) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)a.ncols * nr) return;
+    const int col = (int)(t % a.ncols), r = (int)(t / a.ncols);
+    const int s0 = r * CAR_L, s1 = min(s0 + CAR_L, a.nseg);
+    const Decay<T, KMODE> dc(a, col);
+    for (int dir = 0; dir < 2; ++dir) {
+        cx<double> c{0.0, 0.0}, D{1.0, 0.0};
+        walk<T, KMODE, false>(a, dc, dir, col, s0, s1, c, D);
+        const int64_t o = (((int64_t)dir * a.ncols + col) * nr + r) * 2;
+        rc[o] = c;
+        rc[o + 1] = D;
+    }
+}
+
+// (2) one work-group per column: exclusive scan of the range transfers in the
+// direction of propagation; leaves the carry into each range in rc[.].c
+__global__ __launch_bounds__(256) void k_cscan(int ncols, int nr, cx<double> *rc) {
+    __shared__ cx<double> sc[256], sd[256];
+    const int col = blockIdx.x, t = threadIdx.x;
+    const int per = (nr + 255) / 256;
+    for (int dir = 0; dir < 2; ++dir) {
+        cx<double> *base = rc + ((int64_t)dir * ncols + col) * nr * 2;
+        // thread t owns propagation positions [t*per, (t+1)*per)
+        auto at = [&](int pos) { return dir ? nr - 1 - pos : pos; };
+        cx<double> c{0.0, 0.0}, D{1.0, 0.0};
+        for (int k = 0; k < per; ++k) {
+            const int pos = t * per + k;
+            if (pos < nr) {
+                const int r = at(pos);
+                cx<double> cr = base[2 * r], Dr = base[2 * r + 1];
+                compose(cr, Dr, c, D);
+                c = cr;
+                D = Dr;
+            }
         }
+        sc[t] = c;
+        sd[t] = D;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            cx<double> pc{0.0, 0.0}, pd{1.0, 0.0};
+            const bool has = t >= off;
+            if (has) {
+                pc = sc[t - off];
+                pd = sd[t - off];
+            }
+            __syncthreads();
+            if (has) compose(c, D, pc, pd);
+            sc[t] = c;
+            sd[t] = D;
+            __syncthreads();
+        }
+        cx<double> cin = t > 0 ? sc[t - 1] : cx<double>{0.0, 0.0};
+        __syncthreads();
+        for (int k = 0; k < per; ++k) {
+            const int pos = t * per + k;
+            if (pos < nr) {
+                const int r = at(pos);
+                const cx<double> cr = base[2 * r], Dr = base[2 * r + 1];
+                base[2 * r] = cin;
+                cx<double> nc = cr, nD = Dr;
+                compose(nc, nD, cin, cx<double>{0.0, 0.0});
+                cin = nc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// (3) one thread per (column, range): re-walk the range from its carry-in,
+// replacing every aggregate by the segment's carry-in
+template <typename T, bool KMODE>
+__global__ __launch_bounds__(256) void k_capply(const CArgs<T> a, int nr, const cx<double> *rc) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)a.ncols * nr) return;
+    const int col = (int)(t % a.ncols), r = (int)(t / a.ncols);
+    const int s0 = r * CAR_L, s1 = min(s0 + CAR_L, a.nseg);
+    const Decay<T, KMODE> dc(a, col);
+    for (int dir = 0; dir < 2; ++dir) {
+        cx<double> c = rc[(((int64_t)dir * a.ncols + col) * nr + r) * 2], D{1.0, 0.0};
+        walk<T, KMODE, true>(a, dc, dir, col, s0, s1, c, D);
+    }
+}
+
+template <typename T, bool KMODE>
+q2d_status carry_run(Plan *p, const CArgs<T> &ca) {
+    const int nr = (ca.nseg + CAR_L - 1) / CAR_L;
+    q2d_status st = ensure(p, p->carry_tmp, (size_t)2 * ca.ncols * nr * 2 * sizeof(cx<double>));
+    if (st != Q2D_OK) return st;
+    cx<double> *rc = (cx<double> *)p->carry_tmp.p;
+    const int64_t nt = (int64_t)ca.ncols * nr;
+    const int nb = (int)((nt + 255) / 256);
+    k_cfold<T, KMODE><<<nb, 256, 0, p->stream>>>(ca, nr, rc);
+    k_cscan<<<ca.ncols, 256, 0, p->stream>>>(ca.ncols, nr, rc);
+    k_capply<T, KMODE><<<nb, 256, 0, p->stream>>>(ca, nr, rc);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
 // per (segment, pair): W = e^{-beta (z_last - z_first)}, G = e^{-beta (z_next_first - z_last)}
@@ -639,8 +728,7 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         ca.coef = ka.coef;
         ca.cstride = cstride;
         ca.moff = ka.moff;
-        k_carry<T, true><<<(ca.ncols + CAR_COLS - 1) / CAR_COLS, CAR_COLS * CAR_RANGES, 0,
-                           p->stream>>>(ca);
+        if ((st = carry_run<T, true>(p, ca)) != Q2D_OK) return st;
         tstart(p, 0);
         dispatch_sweep<T>(p, ka, grid);
         tstop(p, 0);
@@ -674,9 +762,7 @@ q2d_status carry_k0(Plan *p, int nseg, int S, int64_t N) {
     ca.spans = (const cx<double> *)p->spans0.p;
     ca.agg = (cx<double> *)p->agg0.p;
     ca.coef = nullptr;
-    k_carry<double, false><<<(ca.ncols + CAR_COLS - 1) / CAR_COLS, CAR_COLS * CAR_RANGES, 0,
-                             p->stream>>>(ca);
-    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+    return carry_run<double, false>(p, ca);
 }
 
 // spans for the k = 0 segmentation (z in the plan's precision)
