@@ -96,6 +96,16 @@ __device__ inline cx<double> cexpm(double br, double bi, double t) {
 __device__ inline float expm_real(float k, float t) { return __expf(-k * t); }
 __device__ inline double expm_real(double k, double t) { return exp(-k * t); }
 
+// lane exchange inside groups of four lanes (DPP quad permutations)
+__device__ inline float quad_xor1(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ inline float quad_xor2(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+__device__ inline double quad_xor1(double v) { return __shfl_xor(v, 1); }
+__device__ inline double quad_xor2(double v) { return __shfl_xor(v, 2); }
+
 template <typename T>
 struct KArgs {
     int64_t N;
@@ -248,6 +258,7 @@ __device__ inline void sweep_dir(const KArgs<T> &a, int seg, int m, int64_t i0, 
             const T qj = c_q[j];
             const T x = qj * c, y = qj * s;
             const T dk = expm_real(k, c_dz[j]);
+            // explicit FMA chains: X += Re(a T) is two FMAs, not mul+fma+add
             T X, Y, Xd, Yd;
             if (DIR == 0) {
                 // T_j = (T_{j-1} + source_{j-1}) e^{-beta dz_j}
@@ -261,13 +272,22 @@ __device__ inline void sweep_dir(const KArgs<T> &a, int seg, int m, int64_t i0, 
 #pragma unroll
                 for (int l = 0; l < MH; ++l) {
                     const cx<T> d = c_d[l][j];
-                    const cx<T> tx = cmul(px[l], d), ty = cmul(py[l], d);
-                    X += alr[l] * tx.re - ali[l] * tx.im;
-                    Xd += adr[l] * tx.re - adi[l] * tx.im;
-                    Y += alr[l] * ty.re - ali[l] * ty.im;
-                    Yd += adr[l] * ty.re - adi[l] * ty.im;
-                    px[l] = cx<T>{tx.re + x, tx.im};
-                    py[l] = cx<T>{ty.re + y, ty.im};
+                    const T txr = fma(px[l].re, d.re, -px[l].im * d.im);
+                    const T txi = fma(px[l].re, d.im, px[l].im * d.re);
+                    const T tyr = fma(py[l].re, d.re, -py[l].im * d.im);
+                    const T tyi = fma(py[l].re, d.im, py[l].im * d.re);
+                    X = fma(alr[l], txr, X);
+                    X = fma(-ali[l], txi, X);
+                    Xd = fma(adr[l], txr, Xd);
+                    Xd = fma(-adi[l], txi, Xd);
+                    Y = fma(alr[l], tyr, Y);
+                    Y = fma(-ali[l], tyi, Y);
+                    Yd = fma(adr[l], tyr, Yd);
+                    Yd = fma(-adi[l], tyi, Yd);
+                    px[l].re = txr + x;
+                    px[l].im = txi;
+                    py[l].re = tyr + y;
+                    py[l].im = tyi;
                 }
             } else {
                 // B_j is the pending state; B_{j-1} = (B_j + source_j) e^{-beta dz_j}
@@ -280,12 +300,20 @@ __device__ inline void sweep_dir(const KArgs<T> &a, int seg, int m, int64_t i0, 
 #pragma unroll
                 for (int l = 0; l < MH; ++l) {
                     const cx<T> d = c_d[l][j];
-                    X += alr[l] * px[l].re - ali[l] * px[l].im;
-                    Xd += adr[l] * px[l].re - adi[l] * px[l].im;
-                    Y += alr[l] * py[l].re - ali[l] * py[l].im;
-                    Yd += adr[l] * py[l].re - adi[l] * py[l].im;
-                    px[l] = cmul(cx<T>{px[l].re + x, px[l].im}, d);
-                    py[l] = cmul(cx<T>{py[l].re + y, py[l].im}, d);
+                    const T bxr = px[l].re, bxi = px[l].im, byr = py[l].re, byi = py[l].im;
+                    X = fma(alr[l], bxr, X);
+                    X = fma(-ali[l], bxi, X);
+                    Xd = fma(adr[l], bxr, Xd);
+                    Xd = fma(-adi[l], bxi, Xd);
+                    Y = fma(alr[l], byr, Y);
+                    Y = fma(-ali[l], byi, Y);
+                    Yd = fma(adr[l], byr, Yd);
+                    Yd = fma(-adi[l], byi, Yd);
+                    const T sxr = bxr + x, syr = byr + y;
+                    px[l].re = fma(sxr, d.re, -bxi * d.im);
+                    px[l].im = fma(sxr, d.im, bxi * d.re);
+                    py[l].re = fma(syr, d.re, -byi * d.im);
+                    py[l].im = fma(syr, d.im, byi * d.re);
                 }
             }
             const T oq = om * (s * X - c * Y);
@@ -304,8 +332,8 @@ __device__ inline void sweep_dir(const KArgs<T> &a, int seg, int m, int64_t i0, 
                 T sum = 0;
 #pragma unroll
                 for (int L = 0; L < WAVE / 4; ++L) sum += red[rj][v][part * (WAVE / 4) + L];
-                sum += __shfl_xor(sum, 1);
-                sum += __shfl_xor(sum, 2);
+                sum += quad_xor1(sum);
+                sum += quad_xor2(sum);
                 if (part == 0 && rj <= r) {
                     const int pj = jj - r + rj;
                     const int jpart = DIR ? nb - 1 - pj : pj;
