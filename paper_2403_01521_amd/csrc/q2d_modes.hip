@@ -115,6 +115,7 @@ __device__ inline double mh_weight(int mx, int my, double alpha, double Lx, doub
 }
 
 constexpr int SAMPLER_RESERVE = 64;
+constexpr int SAMPLER_LDS = 2048;  // proposals staged in LDS for the walk
 
 // One block: parallel proposals, then the sequential accept/reject walk.
 __global__ __launch_bounds__(1024) void k_sample(int P, int D, uint64_t seed, uint64_t step,
@@ -144,7 +145,47 @@ __global__ __launch_bounds__(1024) void k_sample(int P, int D, uint64_t seed, ui
         uacc[e] = u53(a[0], a[1]);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    // the sequential walk reads the proposals from LDS
+    __shared__ int32_t lx[SAMPLER_LDS], ly[SAMPLER_LDS];
+    __shared__ double lw[SAMPLER_LDS], lu[SAMPLER_LDS];
+    const bool in_lds = n <= SAMPLER_LDS;
+    if (in_lds) {
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            lx[e] = prop[2 * e];
+            ly[e] = prop[2 * e + 1];
+            lw[e] = wgt[e];
+            lu[e] = uacc[e];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && in_lds) {
+        int e0 = -1;
+        for (int e = 0; e < SAMPLER_RESERVE; ++e)
+            if (lx[e] != 0 || ly[e] != 0) {
+                e0 = e;
+                break;
+            }
+        if (e0 < 0) {
+            atomicOr(status, 1 << Q2D_ESAMPLER);
+            e0 = 0;
+        }
+        int cx_ = lx[e0], cy_ = ly[e0];
+        double wc = lw[e0];
+        for (int t = 1; t <= P * D; ++t) {
+            const int e = e0 + t;
+            if (lu[e] < lw[e] / wc) {
+                cx_ = lx[e];
+                cy_ = ly[e];
+                wc = lw[e];
+            }
+            if (t % D == 0) {
+                const int pidx = t / D - 1;
+                modes[pidx] = cx_;
+                modes[p_pad + pidx] = cy_;
+            }
+        }
+    }
+    if (threadIdx.x == 0 && !in_lds) {
         int e0 = -1;
         for (int e = 0; e < SAMPLER_RESERVE; ++e)
             if (prop[2 * e] != 0 || prop[2 * e + 1] != 0) {

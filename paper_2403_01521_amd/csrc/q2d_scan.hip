@@ -404,7 +404,7 @@ struct CArgs {
     int64_t cstride, moff;
 };
 
-constexpr int CAR_L = 32;      // segments per range
+constexpr int CAR_L = 8;       // segments per range
 constexpr int CAR_BATCH = 4;   // loads issued ahead of the dependent chain
 
 // Compose two range transfers x -> c + D x: first (c1, D1), then (c2, D2).
