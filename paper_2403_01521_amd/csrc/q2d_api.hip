@@ -461,7 +461,7 @@ q2d_status q2d_long_range(q2d_plan_t p, const void *pos, const void *q, int64_t 
         if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
         if (p->n_exact > 0 &&
             (st = kmodes_run(p, N, (const int32_t *)p->exact_modes.p, p->exact_coef.p,
-                             p->n_exact_pad, 0, p->n_exact, false, &nch)) != Q2D_OK)
+                             p->n_exact_pad, 0, p->n_exact, &nch)) != Q2D_OK)
             return st;
         if ((st = k0_run(p, N)) != Q2D_OK) return st;
     }
@@ -488,7 +488,7 @@ q2d_status q2d_rbm_step(q2d_plan_t p, const void *pos, const void *q, int64_t N,
     if (N > 0) {
         if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
         if ((st = kmodes_run(p, N, (const int32_t *)p->rb_modes.p, p->rb_coef.p, p_pad, 0, P,
-                             false, &nch)) != Q2D_OK)
+                             &nch)) != Q2D_OK)
             return st;
         if ((st = k0_run(p, N)) != Q2D_OK) return st;
     }

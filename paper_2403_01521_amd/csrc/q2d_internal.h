@@ -130,10 +130,10 @@ q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_
 // random-batch sampler: writes p->rb_modes and p->rb_coef for P modes
 q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step);
 
-// k != 0 part over a mode table: accumulates per-particle outputs into outk
+// k != 0 part over a mode table: per-particle outputs in n_chunks_out chunks
+// of outk, to be summed
 q2d_status kmodes_run(Plan *p, int64_t N, const int32_t *modes, const void *coef,
-                      int64_t coef_stride, int64_t mode_off, int64_t n_modes, bool accumulate,
-                      int *n_chunks_out);
+                      int64_t coef_stride, int64_t mode_off, int64_t n_modes, int *n_chunks_out);
 
 // k = 0 term: writes p->phi0, p->fz0 (FP64, sorted order)
 q2d_status k0_run(Plan *p, int64_t N);

@@ -26,6 +26,8 @@
 //    product of rounded ratios;
 //  * the per-particle results are reduced over the 64 mode lanes through a
 //    padded LDS transpose in a fixed order (deterministic).
+#include <algorithm>
+
 #include "q2d_internal.h"
 
 namespace q2d {
@@ -106,6 +108,22 @@ __device__ inline float quad_xor2(float v) {
 __device__ inline double quad_xor1(double v) { return __shfl_xor(v, 1); }
 __device__ inline double quad_xor2(double v) { return __shfl_xor(v, 2); }
 
+// A launch is a list of units along the (1-D) grid.  A unit is a set of
+// modes that shares one lane layout: F consecutive segments per wave and
+// wb = 64 / F modes per segment group.  F = 1: whole groups of 64 modes, a
+// wave loops over the unit's groups; F > 1: one band of wb < 64 modes, so a
+// wave still has every lane busy.  All units use the same segments (S
+// particles), hence one carry scan serves them all.
+constexpr int MAX_UNITS = 32;
+struct Unit {
+    int F;      // segments per wave
+    int m0;     // first mode (within the launch's mode batch)
+    int nm;     // modes in the unit
+    int chunk;  // output chunk
+    int b0;     // first work-group of the unit
+    int acc;    // add to the chunk (an earlier mode batch wrote it)
+};
+
 template <typename T>
 struct KArgs {
     int64_t N;
@@ -116,17 +134,49 @@ struct KArgs {
     int64_t mstride;  // my of mode m at modes[mstride + m]
     const T *coef;
     int64_t cstride;  // field f of mode m at coef[f * cstride + m]
-    int64_t moff;
-    int nmodes, ngroups, gpc, gpad;
+    int64_t moff;     // first mode of the batch in the tables
+    int nmodes, gpad;
+    int nunits;
+    Unit units[MAX_UNITS];
     T bre[MAX_PAIRS], bim[MAX_PAIRS];
     cx<T> *agg;  // [2 dirs][nseg][MH+1 slots][2 inputs][gpad]
     T *outk;     // [chunks][N][4]
-    int accumulate;
 };
 
 template <int MH>
 __device__ inline int64_t agg_idx(int nseg, int gpad, int dir, int seg, int slot, int inp, int m) {
     return ((((int64_t)dir * nseg + seg) * (MH + 1) + slot) * 2 + inp) * gpad + m;
+}
+
+// This work-group's unit and lane layout.  Lane L works on segment
+// (wave * F + L / wb) for modes m0 + g * wb + L % wb.  The F segments
+// advance in lock step; a block of wb steps covers 64 particles (wb from
+// each segment), which the lanes load cooperatively, one each: lane L loads
+// step L % wb of segment L / wb into LDS entry (L % wb) * F + L / wb.
+struct LaneMap {
+    Unit u;
+    int wb, wave;
+    int f, mi, seg;
+    int64_t i0;  // first particle of this lane's segment
+    int n;       // its length (0 if past the last segment)
+};
+
+template <typename T>
+__device__ inline LaneMap lane_map(const KArgs<T> &a) {
+    LaneMap r;
+    int k = 0;
+    for (int t = 1; t < a.nunits; ++t)
+        if ((int)blockIdx.x >= a.units[t].b0) k = t;
+    r.u = a.units[k];
+    r.wb = WAVE / r.u.F;
+    r.wave = (int)blockIdx.x - r.u.b0;
+    const int lane = threadIdx.x;
+    r.f = lane / r.wb;
+    r.mi = lane % r.wb;
+    r.seg = r.wave * r.u.F + r.f;
+    r.i0 = (int64_t)r.seg * a.S;
+    r.n = r.seg < a.nseg ? (int)(min(r.i0 + (int64_t)a.S, a.N) - r.i0) : 0;
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -135,17 +185,22 @@ __device__ inline int64_t agg_idx(int nseg, int gpad, int dir, int seg, int slot
 template <typename T, int MH>
 __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
     using U = typename Tr<T>::U;
-    const int seg = blockIdx.x, chunk = blockIdx.y, lane = threadIdx.x;
-    const int64_t i0 = (int64_t)seg * a.S;
-    const int64_t i1 = min(i0 + (int64_t)a.S, a.N);
+    const int lane = threadIdx.x;
+    const LaneMap lm = lane_map(a);
+    const int BS = lm.wb;  // steps per block; lane loads segment f = lane / BS, step lane % BS
     __shared__ U c_ux[WAVE], c_uy[WAVE];
     __shared__ T c_q[WAVE], c_zf[WAVE], c_zb[WAVE];
     __shared__ cx<T> c_ef[MH][WAVE], c_eb[MH][WAVE];
-    const T zfirst = a.z[i0], zlast = a.z[i1 - 1];
-    const int g0 = chunk * a.gpc, g1 = min(g0 + a.gpc, a.ngroups);
-    for (int g = g0; g < g1; ++g) {
-        const int m = g * WAVE + lane;
-        const bool mv = m < a.nmodes;
+    // LDS entries are step-major (entry j * F + f): the F segment groups
+    // read F adjacent entries, conflict-free
+    const int js = lane % BS, wi = js * lm.u.F + lm.f;
+    const T s_zf = lm.n > 0 ? a.z[lm.i0] : (T)0, s_zl = lm.n > 0 ? a.z[lm.i0 + lm.n - 1] : (T)0;
+    const int nblk = (a.S + BS - 1) / BS;
+    const int ng = (lm.u.nm + lm.wb - 1) / lm.wb;
+    for (int g = 0; g < ng; ++g) {
+        const int ml = g * lm.wb + lm.mi;
+        const bool mv = ml < lm.u.nm;
+        const int m = lm.u.m0 + ml;
         const int mx = mv ? a.modes[a.moff + m] : 0;
         const int my = mv ? a.modes[a.mstride + a.moff + m] : 0;
         const T k = mv ? a.coef[2 * a.cstride + a.moff + m] : (T)0;
@@ -153,191 +208,249 @@ __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
 #pragma unroll
         for (int l = 0; l < MH; ++l) fx[l] = fy[l] = bx[l] = by[l] = cx<T>{0, 0};
         T fkx = 0, fky = 0, bkx = 0, bky = 0;
-        for (int64_t ib = i0; ib < i1; ib += WAVE) {
-            const int nb = (int)min((int64_t)WAVE, i1 - ib);
+        for (int blk = 0; blk < nblk; ++blk) {
             __syncthreads();
-            if (lane < nb) {
-                const int64_t p = ib + lane;
-                c_ux[lane] = a.ux[p];
-                c_uy[lane] = a.uy[p];
-                c_q[lane] = a.q[p];
+            const int pos = blk * BS + js;
+            if (pos < lm.n) {
+                const int64_t p = lm.i0 + pos;
+                c_ux[wi] = a.ux[p];
+                c_uy[wi] = a.uy[p];
+                c_q[wi] = a.q[p];
                 const T zp = a.z[p];
-                const T tf = zlast - zp, tb = zp - zfirst;
-                c_zf[lane] = tf;
-                c_zb[lane] = tb;
+                const T tf = s_zl - zp, tb = zp - s_zf;
+                c_zf[wi] = tf;
+                c_zb[wi] = tb;
 #pragma unroll
                 for (int l = 0; l < MH; ++l) {
-                    c_ef[l][lane] = cexpm(a.bre[l], a.bim[l], tf);
-                    c_eb[l][lane] = cexpm(a.bre[l], a.bim[l], tb);
+                    c_ef[l][wi] = cexpm(a.bre[l], a.bim[l], tf);
+                    c_eb[l][wi] = cexpm(a.bre[l], a.bim[l], tb);
                 }
             }
             __syncthreads();
-            for (int j = 0; j < nb; ++j) {
-                T s, c;
-                phase_sc(mx, my, c_ux[j], c_uy[j], s, c);
-                const T x = c_q[j] * c, y = c_q[j] * s;
-                const T ef = expm_real(k, c_zf[j]), eb = expm_real(k, c_zb[j]);
-                fkx += x * ef;
-                fky += y * ef;
-                bkx += x * eb;
-                bky += y * eb;
+            for (int j = 0; j < BS; ++j) {
+                if (blk * BS + j < lm.n) {
+                    const int ci = j * lm.u.F + lm.f;
+                    T s, c;
+                    phase_sc(mx, my, c_ux[ci], c_uy[ci], s, c);
+                    const T x = c_q[ci] * c, y = c_q[ci] * s;
+                    const T ef = expm_real(k, c_zf[ci]), eb = expm_real(k, c_zb[ci]);
+                    fkx += x * ef;
+                    fky += y * ef;
+                    bkx += x * eb;
+                    bky += y * eb;
 #pragma unroll
-                for (int l = 0; l < MH; ++l) {
-                    const cx<T> e = c_ef[l][j];
-                    fx[l].re += x * e.re;
-                    fx[l].im += x * e.im;
-                    fy[l].re += y * e.re;
-                    fy[l].im += y * e.im;
-                    const cx<T> e2 = c_eb[l][j];
-                    bx[l].re += x * e2.re;
-                    bx[l].im += x * e2.im;
-                    by[l].re += y * e2.re;
-                    by[l].im += y * e2.im;
+                    for (int l = 0; l < MH; ++l) {
+                        const cx<T> e = c_ef[l][ci];
+                        fx[l].re += x * e.re;
+                        fx[l].im += x * e.im;
+                        fy[l].re += y * e.re;
+                        fy[l].im += y * e.im;
+                        const cx<T> e2 = c_eb[l][ci];
+                        bx[l].re += x * e2.re;
+                        bx[l].im += x * e2.im;
+                        by[l].re += y * e2.re;
+                        by[l].im += y * e2.im;
+                    }
                 }
             }
         }
+        // every column below gpad is written (a padded mode's aggregates are
+        // finite and meet zero coefficients in the sweep)
+        if (lm.seg < a.nseg && m < a.gpad) {
+            const int seg = lm.seg;
 #pragma unroll
-        for (int l = 0; l < MH; ++l) {
-            a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, l, 0, m)] = fx[l];
-            a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, l, 1, m)] = fy[l];
-            a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, l, 0, m)] = bx[l];
-            a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, l, 1, m)] = by[l];
+            for (int l = 0; l < MH; ++l) {
+                a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, l, 0, m)] = fx[l];
+                a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, l, 1, m)] = fy[l];
+                a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, l, 0, m)] = bx[l];
+                a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, l, 1, m)] = by[l];
+            }
+            a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 0, m)] = cx<T>{fkx, 0};
+            a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 1, m)] = cx<T>{fky, 0};
+            a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 0, m)] = cx<T>{bkx, 0};
+            a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 1, m)] = cx<T>{bky, 0};
         }
-        a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 0, m)] = cx<T>{fkx, 0};
-        a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 1, m)] = cx<T>{fky, 0};
-        a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 0, m)] = cx<T>{bkx, 0};
-        a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 1, m)] = cx<T>{bky, 0};
     }
 }
 
 // ---------------------------------------------------------------------------
-// pass 3: the sweep (recursion) of one segment for the lanes' modes
+// pass 3: the sweep (recursion) through each lane's segment for its mode
 // ---------------------------------------------------------------------------
-constexpr int SMAX = 512;  // largest segment
-constexpr int SUB = 4;     // particles per lane-reduction round
+constexpr int SMAX = 512;  // longest segment
+constexpr int SUB = 4;     // steps per lane-reduction round
 
 template <typename T, int MH, int DIR>
-__device__ inline void sweep_dir(const KArgs<T> &a, int seg, int m, int64_t i0, int64_t i1,
-                                 int mx, int my, T kx, T ky, T k, T om, T ak, T akd,
+__device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, int mx, int my,
+                                 T kx, T ky, T k, T om, T ak, T akd,
                                  const T *alr, const T *ali, const T *adr, const T *adi,
                                  typename Tr<T>::U *c_ux, typename Tr<T>::U *c_uy, T *c_q,
                                  T *c_dz, cx<T> (*c_d)[WAVE], T (*red)[4][WAVE + 1],
-                                 T (*outl)[4]) {
+                                 T *outc, bool store) {
     const int lane = threadIdx.x;
+    const int BS = lm.wb;
     cx<T> px[MH], py[MH];
+    T pkx = 0, pky = 0;
 #pragma unroll
-    for (int l = 0; l < MH; ++l) {
-        px[l] = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, seg, l, 0, m)];
-        py[l] = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, seg, l, 1, m)];
+    for (int l = 0; l < MH; ++l) px[l] = py[l] = cx<T>{0, 0};
+    if (lm.n > 0 && m < a.gpad) {
+#pragma unroll
+        for (int l = 0; l < MH; ++l) {
+            px[l] = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, lm.seg, l, 0, m)];
+            py[l] = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, lm.seg, l, 1, m)];
+        }
+        pkx = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, lm.seg, MH, 0, m)].re;
+        pky = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, lm.seg, MH, 1, m)].re;
     }
-    T pkx = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, seg, MH, 0, m)].re;
-    T pky = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, seg, MH, 1, m)].re;
-    const int ns = (int)(i1 - i0);
-    const int nblk = (ns + WAVE - 1) / WAVE;
+    const int js = lane % BS, wi = js * lm.u.F + lm.f;  // step-major LDS entries
+    const int nblk = (a.S + BS - 1) / BS;
+    const int R = BS < SUB ? BS : SUB;  // steps per reduction round
+    // reduction geometry: lane reads 16 entries of row (lane >> 2)
+    const int rrow = lane >> 2, rchunk = lane & 3;
+    const int rr = rrow >> 2, rv = rrow & 3;
     for (int bb = 0; bb < nblk; ++bb) {
         const int blk = DIR ? (nblk - 1 - bb) : bb;
-        const int64_t ib = i0 + (int64_t)blk * WAVE;
-        const int nb = (int)min((int64_t)WAVE, i1 - ib);
         __syncthreads();
-        if (lane < nb) {
-            const int64_t p = ib + lane;
-            c_ux[lane] = a.ux[p];
-            c_uy[lane] = a.uy[p];
-            c_q[lane] = a.q[p];
-            // gap to the particle below inside this segment (0 at its first one)
-            const T dz = (p > i0) ? a.z[p] - a.z[p - 1] : (T)0;
-            c_dz[lane] = dz;
+        {
+            const int pos = blk * BS + js;
+            if (pos < lm.n) {
+                const int64_t p = lm.i0 + pos;
+                c_ux[wi] = a.ux[p];
+                c_uy[wi] = a.uy[p];
+                c_q[wi] = a.q[p];
+                // gap to the particle below inside the segment (0 at its first one)
+                const T dz = pos > 0 ? a.z[p] - a.z[p - 1] : (T)0;
+                c_dz[wi] = dz;
 #pragma unroll
-            for (int l = 0; l < MH; ++l) c_d[l][lane] = cexpm(a.bre[l], a.bim[l], dz);
+                for (int l = 0; l < MH; ++l) c_d[l][wi] = cexpm(a.bre[l], a.bim[l], dz);
+            }
         }
         __syncthreads();
-        for (int jj = 0; jj < nb; ++jj) {
-            const int j = DIR ? nb - 1 - jj : jj;
-            T s, c;
-            phase_sc(mx, my, c_ux[j], c_uy[j], s, c);
-            const T qj = c_q[j];
-            const T x = qj * c, y = qj * s;
-            const T dk = expm_real(k, c_dz[j]);
-            // explicit FMA chains: X += Re(a T) is two FMAs, not mul+fma+add
-            T X, Y, Xd, Yd;
-            if (DIR == 0) {
-                // T_j = (T_{j-1} + source_{j-1}) e^{-beta dz_j}
-                const T tkx = pkx * dk, tky = pky * dk;
-                X = ak * tkx;
-                Xd = akd * tkx;
-                Y = ak * tky;
-                Yd = akd * tky;
-                pkx = tkx + x;
-                pky = tky + y;
+        for (int jj = 0; jj < BS; ++jj) {
+            const int j = DIR ? BS - 1 - jj : jj;
+            const int r = jj % R;
+            T o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+            if (blk * BS + j < lm.n) {
+                const int ci = j * lm.u.F + lm.f;
+                T s, c;
+                phase_sc(mx, my, c_ux[ci], c_uy[ci], s, c);
+                const T qj = c_q[ci];
+                const T x = qj * c, y = qj * s;
+                const T dk = expm_real(k, c_dz[ci]);
+                // explicit FMA chains: X += Re(a T) is two FMAs, not mul+fma+add
+                T X, Y, Xd, Yd;
+                if (DIR == 0) {
+                    // T_j = (T_{j-1} + source_{j-1}) e^{-beta dz_j}
+                    const T tkx = pkx * dk, tky = pky * dk;
+                    X = ak * tkx;
+                    Xd = akd * tkx;
+                    Y = ak * tky;
+                    Yd = akd * tky;
+                    pkx = tkx + x;
+                    pky = tky + y;
 #pragma unroll
-                for (int l = 0; l < MH; ++l) {
-                    const cx<T> d = c_d[l][j];
-                    const T txr = fma(px[l].re, d.re, -px[l].im * d.im);
-                    const T txi = fma(px[l].re, d.im, px[l].im * d.re);
-                    const T tyr = fma(py[l].re, d.re, -py[l].im * d.im);
-                    const T tyi = fma(py[l].re, d.im, py[l].im * d.re);
-                    X = fma(alr[l], txr, X);
-                    X = fma(-ali[l], txi, X);
-                    Xd = fma(adr[l], txr, Xd);
-                    Xd = fma(-adi[l], txi, Xd);
-                    Y = fma(alr[l], tyr, Y);
-                    Y = fma(-ali[l], tyi, Y);
-                    Yd = fma(adr[l], tyr, Yd);
-                    Yd = fma(-adi[l], tyi, Yd);
-                    px[l].re = txr + x;
-                    px[l].im = txi;
-                    py[l].re = tyr + y;
-                    py[l].im = tyi;
-                }
-            } else {
-                // B_j is the pending state; B_{j-1} = (B_j + source_j) e^{-beta dz_j}
-                X = ak * pkx;
-                Xd = akd * pkx;
-                Y = ak * pky;
-                Yd = akd * pky;
-                pkx = (pkx + x) * dk;
-                pky = (pky + y) * dk;
+                    for (int l = 0; l < MH; ++l) {
+                        const cx<T> d = c_d[l][ci];
+                        const T txr = fma(px[l].re, d.re, -px[l].im * d.im);
+                        const T txi = fma(px[l].re, d.im, px[l].im * d.re);
+                        const T tyr = fma(py[l].re, d.re, -py[l].im * d.im);
+                        const T tyi = fma(py[l].re, d.im, py[l].im * d.re);
+                        X = fma(alr[l], txr, X);
+                        X = fma(-ali[l], txi, X);
+                        Xd = fma(adr[l], txr, Xd);
+                        Xd = fma(-adi[l], txi, Xd);
+                        Y = fma(alr[l], tyr, Y);
+                        Y = fma(-ali[l], tyi, Y);
+                        Yd = fma(adr[l], tyr, Yd);
+                        Yd = fma(-adi[l], tyi, Yd);
+                        px[l].re = txr + x;
+                        px[l].im = txi;
+                        py[l].re = tyr + y;
+                        py[l].im = tyi;
+                    }
+                } else {
+                    // B_j is the pending state; B_{j-1} = (B_j + source_j) e^{-beta dz_j}
+                    X = ak * pkx;
+                    Xd = akd * pkx;
+                    Y = ak * pky;
+                    Yd = akd * pky;
+                    pkx = (pkx + x) * dk;
+                    pky = (pky + y) * dk;
 #pragma unroll
-                for (int l = 0; l < MH; ++l) {
-                    const cx<T> d = c_d[l][j];
-                    const T bxr = px[l].re, bxi = px[l].im, byr = py[l].re, byi = py[l].im;
-                    X = fma(alr[l], bxr, X);
-                    X = fma(-ali[l], bxi, X);
-                    Xd = fma(adr[l], bxr, Xd);
-                    Xd = fma(-adi[l], bxi, Xd);
-                    Y = fma(alr[l], byr, Y);
-                    Y = fma(-ali[l], byi, Y);
-                    Yd = fma(adr[l], byr, Yd);
-                    Yd = fma(-adi[l], byi, Yd);
-                    const T sxr = bxr + x, syr = byr + y;
-                    px[l].re = fma(sxr, d.re, -bxi * d.im);
-                    px[l].im = fma(sxr, d.im, bxi * d.re);
-                    py[l].re = fma(syr, d.re, -byi * d.im);
-                    py[l].im = fma(syr, d.im, byi * d.re);
+                    for (int l = 0; l < MH; ++l) {
+                        const cx<T> d = c_d[l][ci];
+                        const T bxr = px[l].re, bxi = px[l].im, byr = py[l].re, byi = py[l].im;
+                        X = fma(alr[l], bxr, X);
+                        X = fma(-ali[l], bxi, X);
+                        Xd = fma(adr[l], bxr, Xd);
+                        Xd = fma(-adi[l], bxi, Xd);
+                        Y = fma(alr[l], byr, Y);
+                        Y = fma(-ali[l], byi, Y);
+                        Yd = fma(adr[l], byr, Yd);
+                        Yd = fma(-adi[l], byi, Yd);
+                        const T sxr = bxr + x, syr = byr + y;
+                        px[l].re = fma(sxr, d.re, -bxi * d.im);
+                        px[l].im = fma(sxr, d.im, bxi * d.re);
+                        py[l].re = fma(syr, d.re, -byi * d.im);
+                        py[l].im = fma(syr, d.im, byi * d.re);
+                    }
                 }
+                const T oq = om * (s * X - c * Y);
+                o0 = om * (c * X + s * Y);
+                o1 = kx * oq;
+                o2 = ky * oq;
+                o3 = -om * (c * Xd + s * Yd);
             }
-            const T oq = om * (s * X - c * Y);
-            const int r = jj % SUB;
-            red[r][0][lane] = om * (c * X + s * Y);
-            red[r][1][lane] = kx * oq;
-            red[r][2][lane] = ky * oq;
-            red[r][3][lane] = -om * (c * Xd + s * Yd);
-            if (r == SUB - 1 || jj == nb - 1) {
-                // 16 (particle, value) sums of 64 lane contributions: 4 lanes per
-                // sum, 16 entries each (rows padded to 65: conflict-free), then a
-                // quad reduction
+            red[r][0][lane] = o0;
+            red[r][1][lane] = o1;
+            red[r][2][lane] = o2;
+            red[r][3][lane] = o3;
+            if (r == R - 1) {
+                // per step and segment group: the sum of 4 outputs over its wb
+                // lanes (rows padded to 65 entries: conflict-free); a lane sums
+                // 16 consecutive entries of one row, then partial sums of a
+                // group wider than 16 lanes are combined by quad exchanges.
+                // The unit's output chunk receives it: stored by the forward
+                // sweep of its first group (store), added otherwise; every
+                // element has one writer per pass and passes are separated
+                // by barriers.
                 __syncthreads();
-                const int pv = lane >> 2, part = lane & 3;
-                const int rj = pv >> 2, v = pv & 3;
-                T sum = 0;
+                if (rr < R) {
+                    const int c0 = rchunk * 16;
+                    const int pj = jj - r + rr;
+                    const int jp = DIR ? BS - 1 - pj : pj;
+                    const int loc = blk * BS + jp;
+                    if (BS >= 16) {
+                        T sum = 0;
 #pragma unroll
-                for (int L = 0; L < WAVE / 4; ++L) sum += red[rj][v][part * (WAVE / 4) + L];
-                sum += quad_xor1(sum);
-                sum += quad_xor2(sum);
-                if (part == 0 && rj <= r) {
-                    const int pj = jj - r + rj;
-                    const int jpart = DIR ? nb - 1 - pj : pj;
-                    outl[(int)(ib - i0) + jpart][v] += sum;
+                        for (int L = 0; L < 16; ++L) sum += red[rr][rv][c0 + L];
+                        if (BS >= 32) sum += quad_xor1(sum);
+                        if (BS >= 64) sum += quad_xor2(sum);
+                        if (c0 % BS == 0) {
+                            const int f = c0 / BS;
+                            const int sf = lm.wave * lm.u.F + f;
+                            const int nf = sf < a.nseg ? (int)(min((int64_t)(sf + 1) * a.S, a.N) -
+                                                                (int64_t)sf * a.S)
+                                                       : 0;
+                            if (loc < nf) {
+                                T *o = outc + ((int64_t)sf * a.S + loc) * 4 + rv;
+                                *o = store ? sum : *o + sum;
+                            }
+                        }
+                    } else {
+                        for (int t = 0; t < 16 / BS; ++t) {
+                            T sum = 0;
+                            for (int L = 0; L < BS; ++L) sum += red[rr][rv][c0 + t * BS + L];
+                            const int f = (c0 + t * BS) / BS;
+                            const int sf = lm.wave * lm.u.F + f;
+                            const int nf = sf < a.nseg ? (int)(min((int64_t)(sf + 1) * a.S, a.N) -
+                                                                (int64_t)sf * a.S)
+                                                       : 0;
+                            if (loc < nf) {
+                                T *o = outc + ((int64_t)sf * a.S + loc) * 4 + rv;
+                                *o = store ? sum : *o + sum;
+                            }
+                        }
+                    }
                 }
                 __syncthreads();
             }
@@ -348,23 +461,17 @@ __device__ inline void sweep_dir(const KArgs<T> &a, int seg, int m, int64_t i0, 
 template <typename T, int MH>
 __global__ __launch_bounds__(64) void k_sweep(const KArgs<T> a) {
     using U = typename Tr<T>::U;
-    const int seg = blockIdx.x, chunk = blockIdx.y, lane = threadIdx.x;
-    const int64_t i0 = (int64_t)seg * a.S;
-    const int64_t i1 = min(i0 + (int64_t)a.S, a.N);
-    const int ns = (int)(i1 - i0);
+    const LaneMap lm = lane_map(a);
     __shared__ U c_ux[WAVE], c_uy[WAVE];
     __shared__ T c_q[WAVE], c_dz[WAVE];
     __shared__ cx<T> c_d[MH][WAVE];
     __shared__ T red[SUB][4][WAVE + 1];
-    __shared__ T outl[SMAX][4];
-    T *outc = a.outk + (int64_t)chunk * a.N * 4;
-    for (int t = lane; t < ns; t += WAVE)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) outl[t][v] = a.accumulate ? outc[(i0 + t) * 4 + v] : (T)0;
-    const int g0 = chunk * a.gpc, g1 = min(g0 + a.gpc, a.ngroups);
-    for (int g = g0; g < g1; ++g) {
-        const int m = g * WAVE + lane;
-        const bool mv = m < a.nmodes;
+    T *outc = a.outk + (int64_t)lm.u.chunk * a.N * 4;
+    const int ng = (lm.u.nm + lm.wb - 1) / lm.wb;
+    for (int g = 0; g < ng; ++g) {
+        const int ml = g * lm.wb + lm.mi;
+        const bool mv = ml < lm.u.nm;
+        const int m = lm.u.m0 + ml;
         auto cf = [&](int f) -> T { return mv ? a.coef[(int64_t)f * a.cstride + a.moff + m] : (T)0; };
         const int mx = mv ? a.modes[a.moff + m] : 0;
         const int my = mv ? a.modes[a.mstride + a.moff + m] : 0;
@@ -379,15 +486,13 @@ __global__ __launch_bounds__(64) void k_sweep(const KArgs<T> a) {
             ndr[l] = -adr[l];
             ndi[l] = -adi[l];
         }
-        sweep_dir<T, MH, 0>(a, seg, m, i0, i1, mx, my, kx, ky, k, om, ak, akd, alr, ali, adr, adi,
-                            c_ux, c_uy, c_q, c_dz, c_d, red, outl);
-        sweep_dir<T, MH, 1>(a, seg, m, i0, i1, mx, my, kx, ky, k, om, ak, -akd, alr, ali, ndr,
-                            ndi, c_ux, c_uy, c_q, c_dz, c_d, red, outl);
+        // lanes of a padded mode (m >= nm) read column m of the aggregates:
+        // gpad covers it, and its zero coefficients null every output
+        sweep_dir<T, MH, 0>(a, lm, m, mx, my, kx, ky, k, om, ak, akd, alr, ali, adr, adi,
+                            c_ux, c_uy, c_q, c_dz, c_d, red, outc, g == 0 && !lm.u.acc);
+        sweep_dir<T, MH, 1>(a, lm, m, mx, my, kx, ky, k, om, ak, -akd, alr, ali, ndr, ndi,
+                            c_ux, c_uy, c_q, c_dz, c_d, red, outc, false);
     }
-    __syncthreads();
-    for (int t = lane; t < ns; t += WAVE)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) outc[(i0 + t) * 4 + v] = outl[t][v];
 }
 
 // ---------------------------------------------------------------------------
@@ -615,16 +720,6 @@ __global__ __launch_bounds__(256) void k_spans(const T *__restrict__ z, int64_t 
     spans[idx * 2 + 1] = cx<double>{m * cs, -m * sn};
 }
 
-template <typename T, int MH>
-void launch_passes(Plan *p, const KArgs<T> &ka, int nchunks_b, dim3 grid) {
-    k_agg<T, MH><<<grid, WAVE, 0, p->stream>>>(ka);
-}
-
-template <typename T, int MH>
-void launch_sweep(Plan *p, const KArgs<T> &ka, dim3 grid) {
-    k_sweep<T, MH><<<grid, WAVE, 0, p->stream>>>(ka);
-}
-
 template <typename T>
 void dispatch_agg(Plan *p, const KArgs<T> &ka, dim3 grid) {
     switch (p->mh) {
@@ -675,41 +770,54 @@ int choose_S(int64_t N) {
     return s;
 }
 
+// Mode decomposition.  All units share segments of S particles (one spans
+// table, one carry scan).  Whole groups of 64 modes run one mode per lane
+// (F = 1), gpc groups per unit; the remaining r < 64 modes split into powers
+// of two w (r = 32 + 4 for P = 100), each a band unit with F = 64 / w
+// segments per wave, so every lane holds a mode and every wave sweeps S
+// particles.  Mode tables longer than MB run in batches; bands join the last.
+// Output chunks: one per unit (batches add into the F = 1 ones).
 template <typename T>
 q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coef,
-                       int64_t cstride, int64_t moff0, int64_t nmodes, bool accumulate,
-                       int *nchunks_out) {
+                       int64_t cstride, int64_t moff0, int64_t nmodes, int *nchunks_out) {
     using U = typename Tr<T>::U;
     *nchunks_out = 0;
     if (nmodes <= 0 || N <= 0) return Q2D_OK;
     const int S = choose_S(N);
     const int nseg = (int)((N + S - 1) / S);
     const int mh = p->mh;
-    q2d_status st;
-    if ((st = ensure(p, p->spans, (size_t)nseg * mh * 2 * sizeof(cx<double>))) != Q2D_OK) return st;
-    {
-        const int64_t n = (int64_t)nseg * mh;
-        k_spans<T><<<(int)((n + 255) / 256), 256, 0, p->stream>>>((const T *)p->s_z.p, N, S, nseg,
-                                                                   p->pp, (cx<double> *)p->spans.p);
-    }
-    const int64_t MB = env_int("Q2D_MODE_BATCH", 1024);
-    const int64_t nb0 = nmodes < MB ? nmodes : MB;
-    const int ngroups0 = (int)((nb0 + WAVE - 1) / WAVE);
-    // groups per chunk: enough waves to fill the chip, few partial buffers
+    const int64_t MB = ((int64_t)std::max(env_int("Q2D_MODE_BATCH", 1024), 1) + WAVE - 1) / WAVE * WAVE;
+    const int64_t nfull = (nmodes / WAVE) * WAVE;
+    const int rem = (int)(nmodes - nfull);
+    const int nbatch = nfull > 0 ? (int)((nfull + MB - 1) / MB) : 1;
+    const int ngroups0 = (int)(std::min(nfull, MB) / WAVE);
+    // groups per unit: enough waves to fill the chip, few output chunks
     int gpc = env_int("Q2D_GPC", 0);
     if (gpc <= 0) {
         const int target = 2048;
         int nch = (target + nseg - 1) / nseg;
         if (nch > ngroups0) nch = ngroups0;
         if (nch < 1) nch = 1;
-        gpc = (ngroups0 + nch - 1) / nch;
+        gpc = ngroups0 > 0 ? (ngroups0 + nch - 1) / nch : 1;
     }
-    const int nchunks = (ngroups0 + gpc - 1) / gpc;
-    const int gpad0 = ngroups0 * WAVE;
-    const size_t aggsz = (size_t)2 * nseg * (mh + 1) * 2 * gpad0 * sizeof(cx<T>);
-    if ((st = ensure(p, p->agg, aggsz)) != Q2D_OK) return st;
+    int nbands = 0;
+    for (int w = WAVE / 2; w >= 1; w >>= 1) nbands += (rem & w) ? 1 : 0;
+    if (ngroups0 > 0 && (ngroups0 + gpc - 1) / gpc > MAX_UNITS - nbands)
+        gpc = (ngroups0 + MAX_UNITS - nbands - 1) / (MAX_UNITS - nbands);
+    const int nch_full = ngroups0 > 0 ? (ngroups0 + gpc - 1) / gpc : 0;
+    const int nchunks = nch_full + nbands;
+    const int64_t gpad_max = std::min(nfull, MB) + rem;
+    q2d_status st;
+    if ((st = ensure(p, p->spans, (size_t)nseg * mh * 2 * sizeof(cx<double>))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->agg, (size_t)2 * nseg * (mh + 1) * 2 * gpad_max * sizeof(cx<T>))) !=
+        Q2D_OK)
+        return st;
     if ((st = ensure(p, p->outk, (size_t)nchunks * N * 4 * sizeof(T))) != Q2D_OK) return st;
-
+    {
+        const int64_t n = (int64_t)nseg * mh;
+        k_spans<T><<<(int)((n + 255) / 256), 256, 0, p->stream>>>((const T *)p->s_z.p, N, S, nseg,
+                                                                   p->pp, (cx<double> *)p->spans.p);
+    }
     KArgs<T> ka{};
     ka.N = N;
     ka.S = S;
@@ -722,25 +830,42 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
     ka.mstride = cstride;
     ka.coef = (const T *)coef;
     ka.cstride = cstride;
-    ka.gpc = gpc;
     for (int l = 0; l < mh; ++l) {
         ka.bre[l] = (T)p->pp.beta_re[l];
         ka.bim[l] = (T)p->pp.beta_im[l];
     }
     ka.agg = (cx<T> *)p->agg.p;
     ka.outk = (T *)p->outk.p;
-    for (int64_t b0 = 0; b0 < nmodes; b0 += MB) {
-        const int64_t nb = (nmodes - b0) < MB ? (nmodes - b0) : MB;
-        const int ngroups = (int)((nb + WAVE - 1) / WAVE);
-        const int nchunks_b = (ngroups + gpc - 1) / gpc;
+    for (int bi = 0; bi < nbatch; ++bi) {
+        const int64_t b0 = (int64_t)bi * MB;
+        const int nbf = (int)std::max<int64_t>(0, std::min(MB, nfull - b0));
+        const bool last = bi == nbatch - 1;
+        const int ngroups = nbf / WAVE;
+        // bands first: their waves are the slowest per step, dispatched
+        // early they do not form the tail
+        int nu = 0, blocks = 0, nbm = nbf;
+        if (last) {
+            int band = 0;
+            for (int w = WAVE / 2; w >= 1; w >>= 1)
+                if (rem & w) {
+                    const int F = WAVE / w;
+                    ka.units[nu++] = Unit{F, nbm, w, nch_full + band, blocks, 0};
+                    blocks += (nseg + F - 1) / F;
+                    nbm += w;
+                    ++band;
+                }
+        }
+        for (int g = 0; g < ngroups; g += gpc) {
+            const int ng = std::min(gpc, ngroups - g);
+            ka.units[nu++] = Unit{1, g * WAVE, ng * WAVE, g / gpc, blocks, bi > 0 ? 1 : 0};
+            blocks += nseg;
+        }
+        ka.nunits = nu;
         ka.moff = moff0 + b0;
-        ka.nmodes = (int)nb;
-        ka.ngroups = ngroups;
-        ka.gpad = ngroups * WAVE;
-        ka.accumulate = (accumulate || b0 > 0) ? 1 : 0;
-        const dim3 grid(nseg, nchunks_b);
+        ka.nmodes = nbm;
+        ka.gpad = nbm;
         tstart(p, 1);
-        dispatch_agg<T>(p, ka, grid);
+        dispatch_agg<T>(p, ka, dim3(blocks));
         tstop(p, 1);
         CArgs<T> ca{};
         ca.nseg = nseg;
@@ -748,7 +873,7 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         ca.S = S;
         ca.mh = mh;
         ca.gpad = ka.gpad;
-        ca.nmodes = (int)nb;
+        ca.nmodes = nbm;
         ca.N = N;
         ca.z = ka.z;
         ca.spans = (const cx<double> *)p->spans.p;
@@ -758,7 +883,7 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         ca.moff = ka.moff;
         if ((st = carry_run<T, true>(p, ca)) != Q2D_OK) return st;
         tstart(p, 0);
-        dispatch_sweep<T>(p, ka, grid);
+        dispatch_sweep<T>(p, ka, dim3(blocks));
         tstop(p, 0);
     }
     *nchunks_out = nchunks;
@@ -768,12 +893,11 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
 }  // namespace
 
 q2d_status kmodes_run(Plan *p, int64_t N, const int32_t *modes, const void *coef,
-                      int64_t coef_stride, int64_t mode_off, int64_t n_modes, bool accumulate,
-                      int *n_chunks_out) {
+                      int64_t coef_stride, int64_t mode_off, int64_t n_modes, int *n_chunks_out) {
     return p->fp32 ? kmodes_impl<float>(p, N, modes, coef, coef_stride, mode_off, n_modes,
-                                        accumulate, n_chunks_out)
+                                        n_chunks_out)
                    : kmodes_impl<double>(p, N, modes, coef, coef_stride, mode_off, n_modes,
-                                         accumulate, n_chunks_out);
+                                         n_chunks_out);
 }
 
 // exported for the k = 0 pass (same carry algebra, beta = 0 last slot)
