@@ -115,6 +115,8 @@ __device__ inline double quad_xor2(double v) { return __shfl_xor(v, 2); }
 // wave still has every lane busy.  All units use the same segments (S
 // particles), hence one carry scan serves them all.
 constexpr int MAX_UNITS = 32;
+constexpr int SMAX = 512;  // longest segment
+constexpr int SUB = 4;     // steps per unrolled round; every unit has wb >= 4
 struct Unit {
     int F;      // segments per wave
     int m0;     // first mode (within the launch's mode batch)
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
     // read F adjacent entries, conflict-free
     const int js = lane % BS, wi = js * lm.u.F + lm.f;
     const T s_zf = lm.n > 0 ? a.z[lm.i0] : (T)0, s_zl = lm.n > 0 ? a.z[lm.i0 + lm.n - 1] : (T)0;
-    const int nblk = (a.S + BS - 1) / BS;
+    const int nblk = a.S / BS;  // S is a multiple of 64, BS a power of two >= 4
     const int ng = (lm.u.nm + lm.wb - 1) / lm.wb;
     for (int g = 0; g < ng; ++g) {
         const int ml = g * lm.wb + lm.mi;
@@ -210,14 +212,23 @@ __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
         T fkx = 0, fky = 0, bkx = 0, bky = 0;
         for (int blk = 0; blk < nblk; ++blk) {
             __syncthreads();
-            const int pos = blk * BS + js;
-            if (pos < lm.n) {
-                const int64_t p = lm.i0 + pos;
-                c_ux[wi] = a.ux[p];
-                c_uy[wi] = a.uy[p];
-                c_q[wi] = a.q[p];
-                const T zp = a.z[p];
-                const T tf = s_zl - zp, tb = zp - s_zf;
+            {
+                // positions past the segment's end hold a zero source
+                const int pos = blk * BS + js;
+                U ux = 0, uy = 0;
+                T qv = 0, tf = 0, tb = 0;
+                if (pos < lm.n) {
+                    const int64_t p = lm.i0 + pos;
+                    ux = a.ux[p];
+                    uy = a.uy[p];
+                    qv = a.q[p];
+                    const T zp = a.z[p];
+                    tf = s_zl - zp;
+                    tb = zp - s_zf;
+                }
+                c_ux[wi] = ux;
+                c_uy[wi] = uy;
+                c_q[wi] = qv;
                 c_zf[wi] = tf;
                 c_zb[wi] = tb;
 #pragma unroll
@@ -227,9 +238,10 @@ __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
                 }
             }
             __syncthreads();
-            for (int j = 0; j < BS; ++j) {
-                if (blk * BS + j < lm.n) {
-                    const int ci = j * lm.u.F + lm.f;
+            for (int j0 = 0; j0 < BS; j0 += SUB) {
+#pragma unroll
+                for (int jr = 0; jr < SUB; ++jr) {
+                    const int ci = (j0 + jr) * lm.u.F + lm.f;
                     T s, c;
                     phase_sc(mx, my, c_ux[ci], c_uy[ci], s, c);
                     const T x = c_q[ci] * c, y = c_q[ci] * s;
@@ -276,18 +288,25 @@ __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
 // ---------------------------------------------------------------------------
 // pass 3: the sweep (recursion) through each lane's segment for its mode
 // ---------------------------------------------------------------------------
-constexpr int SMAX = 512;  // longest segment
-constexpr int SUB = 4;     // steps per lane-reduction round
+
+// Coefficients of one mode as the sweep uses them, with the mode weight omega
+// and the output signs folded in: X = Re sum_beta al_beta T_beta gives omega X
+// directly, Xd the z-derivative term -omega X' (forward sign; the backward
+// sweep negates ad, since T - B enters the derivative).
+template <typename T, int MH>
+struct SweepCoef {
+    T kx, ky, k, ak, akd;
+    T alr[MH], ali[MH], adr[MH], adi[MH];
+};
 
 template <typename T, int MH, int DIR>
 __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, int mx, int my,
-                                 T kx, T ky, T k, T om, T ak, T akd,
-                                 const T *alr, const T *ali, const T *adr, const T *adi,
-                                 typename Tr<T>::U *c_ux, typename Tr<T>::U *c_uy, T *c_q,
-                                 T *c_dz, cx<T> (*c_d)[WAVE], T (*red)[4][WAVE + 1],
-                                 T *outc, bool store) {
+                                 const SweepCoef<T, MH> &cf, typename Tr<T>::U *c_ux,
+                                 typename Tr<T>::U *c_uy, T *c_q, T *c_dz, cx<T> (*c_d)[WAVE],
+                                 T (*red)[4][WAVE + 1], T *outc, bool store) {
+    using U = typename Tr<T>::U;
     const int lane = threadIdx.x;
-    const int BS = lm.wb;
+    const int BS = lm.wb, F = lm.u.F;
     cx<T> px[MH], py[MH];
     T pkx = 0, pky = 0;
 #pragma unroll
@@ -301,50 +320,57 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
         pkx = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, lm.seg, MH, 0, m)].re;
         pky = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, lm.seg, MH, 1, m)].re;
     }
-    const int js = lane % BS, wi = js * lm.u.F + lm.f;  // step-major LDS entries
-    const int nblk = (a.S + BS - 1) / BS;
-    const int R = BS < SUB ? BS : SUB;  // steps per reduction round
+    const int js = lane % BS, wi = js * F + lm.f;  // step-major LDS entries
+    const int nblk = a.S / BS;                     // S is a multiple of 64
     // reduction geometry: lane reads 16 entries of row (lane >> 2)
     const int rrow = lane >> 2, rchunk = lane & 3;
     const int rr = rrow >> 2, rv = rrow & 3;
+    const int c0 = rchunk * 16;
     for (int bb = 0; bb < nblk; ++bb) {
         const int blk = DIR ? (nblk - 1 - bb) : bb;
         __syncthreads();
         {
+            // positions past the segment's end hold a zero source and a unit
+            // decay: the recursion passes them through unchanged and their
+            // outputs are never stored
             const int pos = blk * BS + js;
+            U ux = 0, uy = 0;
+            T qv = 0, dz = 0;
             if (pos < lm.n) {
                 const int64_t p = lm.i0 + pos;
-                c_ux[wi] = a.ux[p];
-                c_uy[wi] = a.uy[p];
-                c_q[wi] = a.q[p];
-                // gap to the particle below inside the segment (0 at its first one)
-                const T dz = pos > 0 ? a.z[p] - a.z[p - 1] : (T)0;
-                c_dz[wi] = dz;
-#pragma unroll
-                for (int l = 0; l < MH; ++l) c_d[l][wi] = cexpm(a.bre[l], a.bim[l], dz);
+                ux = a.ux[p];
+                uy = a.uy[p];
+                qv = a.q[p];
+                dz = pos > 0 ? a.z[p] - a.z[p - 1] : (T)0;  // gap to the particle below
             }
+            c_ux[wi] = ux;
+            c_uy[wi] = uy;
+            c_q[wi] = qv;
+            c_dz[wi] = dz;
+#pragma unroll
+            for (int l = 0; l < MH; ++l) c_d[l][wi] = cexpm(a.bre[l], a.bim[l], dz);
         }
         __syncthreads();
-        for (int jj = 0; jj < BS; ++jj) {
-            const int j = DIR ? BS - 1 - jj : jj;
-            const int r = jj % R;
-            T o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-            if (blk * BS + j < lm.n) {
-                const int ci = j * lm.u.F + lm.f;
+        for (int r0 = 0; r0 < BS; r0 += SUB) {
+#pragma unroll
+            for (int r = 0; r < SUB; ++r) {
+                const int jj = r0 + r;
+                const int j = DIR ? BS - 1 - jj : jj;
+                const int ci = j * F + lm.f;
                 T s, c;
                 phase_sc(mx, my, c_ux[ci], c_uy[ci], s, c);
                 const T qj = c_q[ci];
                 const T x = qj * c, y = qj * s;
-                const T dk = expm_real(k, c_dz[ci]);
+                const T dk = expm_real(cf.k, c_dz[ci]);
                 // explicit FMA chains: X += Re(a T) is two FMAs, not mul+fma+add
                 T X, Y, Xd, Yd;
                 if (DIR == 0) {
                     // T_j = (T_{j-1} + source_{j-1}) e^{-beta dz_j}
                     const T tkx = pkx * dk, tky = pky * dk;
-                    X = ak * tkx;
-                    Xd = akd * tkx;
-                    Y = ak * tky;
-                    Yd = akd * tky;
+                    X = cf.ak * tkx;
+                    Xd = cf.akd * tkx;
+                    Y = cf.ak * tky;
+                    Yd = cf.akd * tky;
                     pkx = tkx + x;
                     pky = tky + y;
 #pragma unroll
@@ -354,14 +380,14 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
                         const T txi = fma(px[l].re, d.im, px[l].im * d.re);
                         const T tyr = fma(py[l].re, d.re, -py[l].im * d.im);
                         const T tyi = fma(py[l].re, d.im, py[l].im * d.re);
-                        X = fma(alr[l], txr, X);
-                        X = fma(-ali[l], txi, X);
-                        Xd = fma(adr[l], txr, Xd);
-                        Xd = fma(-adi[l], txi, Xd);
-                        Y = fma(alr[l], tyr, Y);
-                        Y = fma(-ali[l], tyi, Y);
-                        Yd = fma(adr[l], tyr, Yd);
-                        Yd = fma(-adi[l], tyi, Yd);
+                        X = fma(cf.alr[l], txr, X);
+                        X = fma(-cf.ali[l], txi, X);
+                        Xd = fma(cf.adr[l], txr, Xd);
+                        Xd = fma(-cf.adi[l], txi, Xd);
+                        Y = fma(cf.alr[l], tyr, Y);
+                        Y = fma(-cf.ali[l], tyi, Y);
+                        Yd = fma(cf.adr[l], tyr, Yd);
+                        Yd = fma(-cf.adi[l], tyi, Yd);
                         px[l].re = txr + x;
                         px[l].im = txi;
                         py[l].re = tyr + y;
@@ -369,24 +395,24 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
                     }
                 } else {
                     // B_j is the pending state; B_{j-1} = (B_j + source_j) e^{-beta dz_j}
-                    X = ak * pkx;
-                    Xd = akd * pkx;
-                    Y = ak * pky;
-                    Yd = akd * pky;
+                    X = cf.ak * pkx;
+                    Xd = -cf.akd * pkx;
+                    Y = cf.ak * pky;
+                    Yd = -cf.akd * pky;
                     pkx = (pkx + x) * dk;
                     pky = (pky + y) * dk;
 #pragma unroll
                     for (int l = 0; l < MH; ++l) {
                         const cx<T> d = c_d[l][ci];
                         const T bxr = px[l].re, bxi = px[l].im, byr = py[l].re, byi = py[l].im;
-                        X = fma(alr[l], bxr, X);
-                        X = fma(-ali[l], bxi, X);
-                        Xd = fma(adr[l], bxr, Xd);
-                        Xd = fma(-adi[l], bxi, Xd);
-                        Y = fma(alr[l], byr, Y);
-                        Y = fma(-ali[l], byi, Y);
-                        Yd = fma(adr[l], byr, Yd);
-                        Yd = fma(-adi[l], byi, Yd);
+                        X = fma(cf.alr[l], bxr, X);
+                        X = fma(-cf.ali[l], bxi, X);
+                        Xd = fma(-cf.adr[l], bxr, Xd);
+                        Xd = fma(cf.adi[l], bxi, Xd);
+                        Y = fma(cf.alr[l], byr, Y);
+                        Y = fma(-cf.ali[l], byi, Y);
+                        Yd = fma(-cf.adr[l], byr, Yd);
+                        Yd = fma(cf.adi[l], byi, Yd);
                         const T sxr = bxr + x, syr = byr + y;
                         px[l].re = fma(sxr, d.re, -bxi * d.im);
                         px[l].im = fma(sxr, d.im, bxi * d.re);
@@ -394,66 +420,56 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
                         py[l].im = fma(syr, d.im, byi * d.re);
                     }
                 }
-                const T oq = om * (s * X - c * Y);
-                o0 = om * (c * X + s * Y);
-                o1 = kx * oq;
-                o2 = ky * oq;
-                o3 = -om * (c * Xd + s * Yd);
+                const T oq = s * X - c * Y;
+                red[r][0][lane] = c * X + s * Y;
+                red[r][1][lane] = cf.kx * oq;
+                red[r][2][lane] = cf.ky * oq;
+                red[r][3][lane] = c * Xd + s * Yd;
             }
-            red[r][0][lane] = o0;
-            red[r][1][lane] = o1;
-            red[r][2][lane] = o2;
-            red[r][3][lane] = o3;
-            if (r == R - 1) {
-                // per step and segment group: the sum of 4 outputs over its wb
-                // lanes (rows padded to 65 entries: conflict-free); a lane sums
-                // 16 consecutive entries of one row, then partial sums of a
-                // group wider than 16 lanes are combined by quad exchanges.
-                // The unit's output chunk receives it: stored by the forward
-                // sweep of its first group (store), added otherwise; every
-                // element has one writer per pass and passes are separated
-                // by barriers.
-                __syncthreads();
-                if (rr < R) {
-                    const int c0 = rchunk * 16;
-                    const int pj = jj - r + rr;
-                    const int jp = DIR ? BS - 1 - pj : pj;
-                    const int loc = blk * BS + jp;
-                    if (BS >= 16) {
-                        T sum = 0;
+            // per step and segment group: the sum of 4 outputs over its wb
+            // lanes (rows padded to 65 entries: conflict-free); a lane sums
+            // 16 consecutive entries of one row, then partial sums of a group
+            // wider than 16 lanes are combined by quad exchanges.  The unit's
+            // output chunk receives it: stored by the forward sweep of its
+            // first group (store), added otherwise; every element has one
+            // writer per pass and passes are separated by barriers.
+            __syncthreads();
+            {
+                const int pj = r0 + rr;
+                const int jp = DIR ? BS - 1 - pj : pj;
+                const int loc = blk * BS + jp;
+                if (BS >= 16) {
+                    T sum = 0;
 #pragma unroll
-                        for (int L = 0; L < 16; ++L) sum += red[rr][rv][c0 + L];
-                        if (BS >= 32) sum += quad_xor1(sum);
-                        if (BS >= 64) sum += quad_xor2(sum);
-                        if (c0 % BS == 0) {
-                            const int f = c0 / BS;
-                            const int sf = lm.wave * lm.u.F + f;
-                            const int nf = sf < a.nseg ? (int)(min((int64_t)(sf + 1) * a.S, a.N) -
-                                                                (int64_t)sf * a.S)
-                                                       : 0;
-                            if (loc < nf) {
-                                T *o = outc + ((int64_t)sf * a.S + loc) * 4 + rv;
-                                *o = store ? sum : *o + sum;
-                            }
+                    for (int L = 0; L < 16; ++L) sum += red[rr][rv][c0 + L];
+                    if (BS >= 32) sum += quad_xor1(sum);
+                    if (BS >= 64) sum += quad_xor2(sum);
+                    if (c0 % BS == 0) {
+                        const int sf = lm.wave * F + c0 / BS;
+                        const int nf = sf < a.nseg ? (int)(min((int64_t)(sf + 1) * a.S, a.N) -
+                                                            (int64_t)sf * a.S)
+                                                   : 0;
+                        if (loc < nf) {
+                            T *o = outc + ((int64_t)sf * a.S + loc) * 4 + rv;
+                            *o = store ? sum : *o + sum;
                         }
-                    } else {
-                        for (int t = 0; t < 16 / BS; ++t) {
-                            T sum = 0;
-                            for (int L = 0; L < BS; ++L) sum += red[rr][rv][c0 + t * BS + L];
-                            const int f = (c0 + t * BS) / BS;
-                            const int sf = lm.wave * lm.u.F + f;
-                            const int nf = sf < a.nseg ? (int)(min((int64_t)(sf + 1) * a.S, a.N) -
-                                                                (int64_t)sf * a.S)
-                                                       : 0;
-                            if (loc < nf) {
-                                T *o = outc + ((int64_t)sf * a.S + loc) * 4 + rv;
-                                *o = store ? sum : *o + sum;
-                            }
+                    }
+                } else {
+                    for (int t = 0; t < 16 / BS; ++t) {
+                        T sum = 0;
+                        for (int L = 0; L < BS; ++L) sum += red[rr][rv][c0 + t * BS + L];
+                        const int sf = lm.wave * F + (c0 + t * BS) / BS;
+                        const int nf = sf < a.nseg ? (int)(min((int64_t)(sf + 1) * a.S, a.N) -
+                                                            (int64_t)sf * a.S)
+                                                   : 0;
+                        if (loc < nf) {
+                            T *o = outc + ((int64_t)sf * a.S + loc) * 4 + rv;
+                            *o = store ? sum : *o + sum;
                         }
                     }
                 }
-                __syncthreads();
             }
+            __syncthreads();
         }
     }
 }
@@ -472,26 +488,28 @@ __global__ __launch_bounds__(64) void k_sweep(const KArgs<T> a) {
         const int ml = g * lm.wb + lm.mi;
         const bool mv = ml < lm.u.nm;
         const int m = lm.u.m0 + ml;
-        auto cf = [&](int f) -> T { return mv ? a.coef[(int64_t)f * a.cstride + a.moff + m] : (T)0; };
+        auto ld = [&](int f) -> T { return mv ? a.coef[(int64_t)f * a.cstride + a.moff + m] : (T)0; };
         const int mx = mv ? a.modes[a.moff + m] : 0;
         const int my = mv ? a.modes[a.mstride + a.moff + m] : 0;
-        const T kx = cf(0), ky = cf(1), k = cf(2), om = cf(3), ak = cf(4), akd = cf(5);
-        T alr[MH], ali[MH], adr[MH], adi[MH], ndr[MH], ndi[MH];
+        const T om = ld(3);
+        SweepCoef<T, MH> cf;
+        cf.kx = ld(0);
+        cf.ky = ld(1);
+        cf.k = ld(2);
+        cf.ak = om * ld(4);
+        cf.akd = -om * ld(5);
 #pragma unroll
         for (int l = 0; l < MH; ++l) {
-            alr[l] = cf(6 + 4 * l);
-            ali[l] = cf(7 + 4 * l);
-            adr[l] = cf(8 + 4 * l);
-            adi[l] = cf(9 + 4 * l);
-            ndr[l] = -adr[l];
-            ndi[l] = -adi[l];
+            cf.alr[l] = om * ld(6 + 4 * l);
+            cf.ali[l] = om * ld(7 + 4 * l);
+            cf.adr[l] = -om * ld(8 + 4 * l);
+            cf.adi[l] = -om * ld(9 + 4 * l);
         }
-        // lanes of a padded mode (m >= nm) read column m of the aggregates:
-        // gpad covers it, and its zero coefficients null every output
-        sweep_dir<T, MH, 0>(a, lm, m, mx, my, kx, ky, k, om, ak, akd, alr, ali, adr, adi,
-                            c_ux, c_uy, c_q, c_dz, c_d, red, outc, g == 0 && !lm.u.acc);
-        sweep_dir<T, MH, 1>(a, lm, m, mx, my, kx, ky, k, om, ak, -akd, alr, ali, ndr, ndi,
-                            c_ux, c_uy, c_q, c_dz, c_d, red, outc, false);
+        // lanes of a padded mode read column m of the aggregates if m < gpad
+        // (finite) and carry zero coefficients: their outputs vanish
+        sweep_dir<T, MH, 0>(a, lm, m, mx, my, cf, c_ux, c_uy, c_q, c_dz, c_d, red, outc,
+                            g == 0 && !lm.u.acc);
+        sweep_dir<T, MH, 1>(a, lm, m, mx, my, cf, c_ux, c_uy, c_q, c_dz, c_d, red, outc, false);
     }
 }
 
@@ -772,9 +790,10 @@ int choose_S(int64_t N) {
 
 // Mode decomposition.  All units share segments of S particles (one spans
 // table, one carry scan).  Whole groups of 64 modes run one mode per lane
-// (F = 1), gpc groups per unit; the remaining r < 64 modes split into powers
-// of two w (r = 32 + 4 for P = 100), each a band unit with F = 64 / w
-// segments per wave, so every lane holds a mode and every wave sweeps S
+// (F = 1), gpc groups per unit; the remaining r < 64 modes, rounded up to a
+// multiple of 4, split into powers of two w >= 4 (r = 32 + 4 for P = 100),
+// each a band unit with F = 64 / w segments per wave, so every lane holds a
+// mode (up to 3 padded lanes in the last band) and every wave sweeps S
 // particles.  Mode tables longer than MB run in batches; bands join the last.
 // Output chunks: one per unit (batches add into the F = 1 ones).
 template <typename T>
@@ -789,6 +808,7 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
     const int64_t MB = ((int64_t)std::max(env_int("Q2D_MODE_BATCH", 1024), 1) + WAVE - 1) / WAVE * WAVE;
     const int64_t nfull = (nmodes / WAVE) * WAVE;
     const int rem = (int)(nmodes - nfull);
+    const int rem4 = (rem + 3) & ~3;  // band lanes, padded to a multiple of 4
     const int nbatch = nfull > 0 ? (int)((nfull + MB - 1) / MB) : 1;
     const int ngroups0 = (int)(std::min(nfull, MB) / WAVE);
     // groups per unit: enough waves to fill the chip, few output chunks
@@ -801,7 +821,7 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         gpc = ngroups0 > 0 ? (ngroups0 + nch - 1) / nch : 1;
     }
     int nbands = 0;
-    for (int w = WAVE / 2; w >= 1; w >>= 1) nbands += (rem & w) ? 1 : 0;
+    for (int w = WAVE / 2; w >= SUB; w >>= 1) nbands += (rem4 & w) ? 1 : 0;
     if (ngroups0 > 0 && (ngroups0 + gpc - 1) / gpc > MAX_UNITS - nbands)
         gpc = (ngroups0 + MAX_UNITS - nbands - 1) / (MAX_UNITS - nbands);
     const int nch_full = ngroups0 > 0 ? (ngroups0 + gpc - 1) / gpc : 0;
@@ -845,13 +865,14 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         // early they do not form the tail
         int nu = 0, blocks = 0, nbm = nbf;
         if (last) {
-            int band = 0;
-            for (int w = WAVE / 2; w >= 1; w >>= 1)
-                if (rem & w) {
-                    const int F = WAVE / w;
-                    ka.units[nu++] = Unit{F, nbm, w, nch_full + band, blocks, 0};
+            int band = 0, left = rem;
+            for (int w = WAVE / 2; w >= SUB; w >>= 1)
+                if (rem4 & w) {
+                    const int F = WAVE / w, nm = std::min(w, left);
+                    ka.units[nu++] = Unit{F, nbm, nm, nch_full + band, blocks, 0};
                     blocks += (nseg + F - 1) / F;
-                    nbm += w;
+                    nbm += nm;
+                    left -= nm;
                     ++band;
                 }
         }
