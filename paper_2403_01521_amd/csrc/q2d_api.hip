@@ -25,6 +25,7 @@ q2d_status ensure(Plan *p, Buf &b, size_t bytes) {
     if (b.bytes >= bytes) return Q2D_OK;
     if (b.p) {
         if (hipStreamSynchronize(p->stream) != hipSuccess) return Q2D_EDEVICE;
+        if (p->side && hipStreamSynchronize(p->side) != hipSuccess) return Q2D_EDEVICE;
         (void)hipFree(b.p);
         b.p = nullptr;
         b.bytes = 0;
@@ -153,6 +154,29 @@ __global__ void k_modes_out(const int32_t *modes, int P, int p_pad, int32_t *out
     }
 }
 
+// Enqueue on the side stream within a scope: the launchers use p->stream.
+struct SideScope {
+    Plan *p;
+    hipStream_t saved;
+    explicit SideScope(Plan *p_) : p(p_), saved(p_->stream) { p->stream = p->side; }
+    ~SideScope() { p->stream = saved; }
+};
+
+// The k = 0 term on the side stream once the sorted data exist; the main
+// stream must wait for ev_k0 before the epilogue reads phi0 / fz0.
+q2d_status k0_side(Plan *p, int64_t N) {
+    if (hipEventRecord(p->ev_sorted, p->stream) != hipSuccess ||
+        hipStreamWaitEvent(p->side, p->ev_sorted, 0) != hipSuccess)
+        return Q2D_EDEVICE;
+    q2d_status st;
+    {
+        SideScope side(p);
+        st = k0_run(p, N);
+    }
+    if (st != Q2D_OK) return st;
+    return hipEventRecord(p->ev_k0, p->side) == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
 }  // namespace
 
 extern "C" {
@@ -250,6 +274,15 @@ q2d_status q2d_plan_create(double Lx, double Ly, double Lz, double alpha, double
     p->stream = (hipStream_t)stream;
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
+        return Q2D_EDEVICE;
+    }
+    if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_sorted, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_modes, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_k0, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        q2d_plan_destroy(p);
         return Q2D_EDEVICE;
     }
 
@@ -410,6 +443,7 @@ q2d_status q2d_plan_destroy(q2d_plan_t p) {
     if (!p) return Q2D_EINVAL;
     (void)hipSetDevice(p->device);
     (void)hipStreamSynchronize(p->stream);
+    if (p->side) (void)hipStreamSynchronize(p->side);
     for (int w = 0; w < 5; ++w) {
         for (auto e : p->pend_ev[w]) (void)hipEventDestroy(e);
         p->pend_ev[w].clear();
@@ -417,9 +451,12 @@ q2d_status q2d_plan_destroy(q2d_plan_t p) {
     Buf *bufs[] = {&p->exact_modes, &p->exact_coef, &p->rb_modes, &p->rb_coef, &p->rb_work,
                    &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
                    &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->carry_tmp, &p->outk, &p->spans0,
-                   &p->agg0, &p->phi0, &p->fz0, &p->epart, &p->status, &p->cell_start,
-                   &p->cell_count, &p->cell_idx, &p->cell_tmp};
+                   &p->agg0, &p->carry_tmp0, &p->phi0, &p->fz0, &p->epart, &p->status,
+                   &p->cell_start, &p->cell_count, &p->cell_idx, &p->cell_tmp};
     for (Buf *b : bufs) free_buf(*b);
+    for (hipEvent_t e : {p->ev_fork, p->ev_sorted, p->ev_modes, p->ev_k0})
+        if (e) (void)hipEventDestroy(e);
+    if (p->side) (void)hipStreamDestroy(p->side);
     delete p;
     return Q2D_OK;
 }
@@ -459,11 +496,12 @@ q2d_status q2d_long_range(q2d_plan_t p, const void *pos, const void *q, int64_t 
     int nch = 0;
     if (N > 0) {
         if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
+        if ((st = k0_side(p, N)) != Q2D_OK) return st;
         if (p->n_exact > 0 &&
             (st = kmodes_run(p, N, (const int32_t *)p->exact_modes.p, p->exact_coef.p,
                              p->n_exact_pad, 0, p->n_exact, &nch)) != Q2D_OK)
             return st;
-        if ((st = k0_run(p, N)) != Q2D_OK) return st;
+        if (hipStreamWaitEvent(p->stream, p->ev_k0, 0) != hipSuccess) return Q2D_EDEVICE;
     }
     st = epilogue(p, N, nch, p->diag_exact, q, phi, F, E);
     tstop(p, 4);
@@ -479,18 +517,30 @@ q2d_status q2d_rbm_step(q2d_plan_t p, const void *pos, const void *q, int64_t N,
     if (p->opts.p_max <= 0) return Q2D_EUNSUPPORTED;
     if (P > p->opts.p_max) return Q2D_ECAPACITY;
     tstart(p, 4);
-    if ((st = sample_modes(p, P, seed, step)) != Q2D_OK) return st;
+    // the sampler runs on the side stream while the main stream sorts
     const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
-    if (modes_out)
-        k_modes_out<<<(P + 255) / 256, 256, 0, p->stream>>>((const int32_t *)p->rb_modes.p, P, p_pad,
-                                                            modes_out);
+    if (hipEventRecord(p->ev_fork, p->stream) != hipSuccess ||
+        hipStreamWaitEvent(p->side, p->ev_fork, 0) != hipSuccess)
+        return Q2D_EDEVICE;
+    {
+        SideScope side(p);
+        if ((st = sample_modes(p, P, seed, step)) != Q2D_OK) return st;
+        if (modes_out)
+            k_modes_out<<<(P + 255) / 256, 256, 0, p->stream>>>((const int32_t *)p->rb_modes.p, P,
+                                                                p_pad, modes_out);
+    }
+    if (hipEventRecord(p->ev_modes, p->side) != hipSuccess) return Q2D_EDEVICE;
     int nch = 0;
     if (N > 0) {
         if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
+        if ((st = k0_side(p, N)) != Q2D_OK) return st;
+        if (hipStreamWaitEvent(p->stream, p->ev_modes, 0) != hipSuccess) return Q2D_EDEVICE;
         if ((st = kmodes_run(p, N, (const int32_t *)p->rb_modes.p, p->rb_coef.p, p_pad, 0, P,
                              &nch)) != Q2D_OK)
             return st;
-        if ((st = k0_run(p, N)) != Q2D_OK) return st;
+        if (hipStreamWaitEvent(p->stream, p->ev_k0, 0) != hipSuccess) return Q2D_EDEVICE;
+    } else if (hipStreamWaitEvent(p->stream, p->ev_modes, 0) != hipSuccess) {
+        return Q2D_EDEVICE;
     }
     st = epilogue(p, N, nch, p->diag_rb, q, phi, F, E);
     tstop(p, 4);

@@ -63,6 +63,10 @@ struct Buf {
 struct Plan {
     int device = 0;
     hipStream_t stream = nullptr;
+    // internal stream for work independent of the mode scans (mode sampling,
+    // the k = 0 term), forked from and joined back into `stream` by events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_sorted = nullptr, ev_modes = nullptr, ev_k0 = nullptr;
     double Lx, Ly, Lz, alpha, rc, kc;
     int M = 0, mh = 0;
     q2d_opts opts{};
@@ -91,8 +95,8 @@ struct Plan {
     Buf carry_tmp;             // per-range transfers of the carry scan
     Buf outk;                  // per-chunk per-particle outputs (T x 4)
 
-    // k = 0 scans
-    Buf spans0, agg0;
+    // k = 0 scans (own carry scratch: they run concurrently with the k != 0 scans)
+    Buf spans0, agg0, carry_tmp0;
     Buf phi0, fz0;             // FP64 per particle (sorted order)
 
     // epilogue and status

@@ -705,11 +705,11 @@ __global__ __launch_bounds__(256) void k_capply(const CArgs<T> a, int nr, const 
 }
 
 template <typename T, bool KMODE>
-q2d_status carry_run(Plan *p, const CArgs<T> &ca) {
+q2d_status carry_run(Plan *p, const CArgs<T> &ca, Buf &tmp) {
     const int nr = (ca.nseg + CAR_L - 1) / CAR_L;
-    q2d_status st = ensure(p, p->carry_tmp, (size_t)2 * ca.ncols * nr * 2 * sizeof(cx<double>));
+    q2d_status st = ensure(p, tmp, (size_t)2 * ca.ncols * nr * 2 * sizeof(cx<double>));
     if (st != Q2D_OK) return st;
-    cx<double> *rc = (cx<double> *)p->carry_tmp.p;
+    cx<double> *rc = (cx<double> *)tmp.p;
     const int64_t nt = (int64_t)ca.ncols * nr;
     const int nb = (int)((nt + 255) / 256);
     k_cfold<T, KMODE><<<nb, 256, 0, p->stream>>>(ca, nr, rc);
@@ -902,7 +902,7 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         ca.coef = ka.coef;
         ca.cstride = cstride;
         ca.moff = ka.moff;
-        if ((st = carry_run<T, true>(p, ca)) != Q2D_OK) return st;
+        if ((st = carry_run<T, true>(p, ca, p->carry_tmp)) != Q2D_OK) return st;
         tstart(p, 0);
         dispatch_sweep<T>(p, ka, dim3(blocks));
         tstop(p, 0);
@@ -935,7 +935,7 @@ q2d_status carry_k0(Plan *p, int nseg, int S, int64_t N) {
     ca.spans = (const cx<double> *)p->spans0.p;
     ca.agg = (cx<double> *)p->agg0.p;
     ca.coef = nullptr;
-    return carry_run<double, false>(p, ca);
+    return carry_run<double, false>(p, ca, p->carry_tmp0);
 }
 
 // spans for the k = 0 segmentation (z in the plan's precision)
