@@ -8,16 +8,23 @@ the FP64 k = 0 term and the reductions, with inputs resident in HBM and a
 different (seed, step) -- hence different modes -- every step.
 
 Prints one JSON line:
-  value        particle-force evaluations per second (N / step time), FP32 path
+  value        particle-force evaluations per second (N / step time), FP32 path,
+               W untimed + K timed steps (default 10 + 100)
   roofline     the hot kernel (k != 0 sweep): algorithmic FLOP per launch over its
                average launch time from HIP events recorded on the plan's stream
-               during the timed steps, against the MI355X FP32 vector peak
+               during the timed steps (the only events recorded there), against
+               the MI355X FP32 vector peak
   cpu_baseline the FP64 O(N) recursion of the oracle on one host core, on all
                1e6 particles but a subset of the modes, scaled to P = 100
-Extra fields: the FP64 path on the same GPU and the FP32/FP64 speedup, and the
-relative RMS difference of FP32 and FP64 forces for identical modes.
+Extra fields: a per-kernel-family breakdown (separate pass with all timers),
+the FP64 path on the same GPU and the FP32/FP64 speedup, the relative RMS
+difference of FP32 and FP64 forces for identical modes, the FP64 exact-k SOE
+sum over all 42,184 modes with e^{-k^2/4 alpha^2} >= 1e-16 (time, and as the
+reference of the random-batch force error per draw and of the running mean over
+the K draws), and the oracle on all host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+                       [--no-exact]
 """
 
 import argparse
@@ -36,6 +43,7 @@ METRIC = "particle-force evals/s at N=1e6 (SOE-RBM FP32 vs FP64 SOE) @ force err
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published)
 P_MODES = 100
 M_SOE = 16
+SEED = 1
 
 
 def flops_per_mode_particle(M):
@@ -51,62 +59,91 @@ def soe_table(M):
     return soe.load_table(os.path.join(ROOT, "tests", "golden", "soe_talbot_M%d.txt" % M))
 
 
-def run_gpu(prec, c, w, s, steps, warmup, timing):
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
     import torch
-    import paper_2403_01521_amd as q2d
-    dt = torch.float32 if prec == "fp32" else torch.float64
-    pos = torch.tensor(c["pos"], dtype=dt, device="cuda")
-    q = torch.tensor(c["q"], dtype=dt, device="cuda")
-    N = len(c["q"])
-    plan = q2d.Plan(c["box"], c["alpha"], w, s, precision=prec, n_max=N, p_max=P_MODES)
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def time_steps(plan, pos, q, steps, warmup, mask):
+    """Wall time per step over `steps` calls (steps 0..steps-1), after `warmup`
+    untimed calls with other step numbers; timers of `mask` recorded."""
+    import torch
     for i in range(warmup):
-        plan.rbm_step(pos, q, P_MODES, seed=1, step=1000000 + i)
+        plan.rbm_step(pos, q, P_MODES, seed=SEED, step=1000000 + i)
     torch.cuda.synchronize()
-    if timing:
-        plan.timing_enable(True)
+    plan.timing_enable(mask)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        plan.rbm_step(pos, q, P_MODES, seed=1, step=i)
+        plan.rbm_step(pos, q, P_MODES, seed=SEED, step=i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    timers = {}
-    if timing:
-        for name, idx in (("sweep", q2d.TIMER_SWEEP), ("agg", q2d.TIMER_AGG),
-                          ("sort", q2d.TIMER_SORT), ("k0", q2d.TIMER_K0), ("call", q2d.TIMER_CALL)):
-            ms, cnt = plan.timing_read(idx)
-            timers[name] = (ms, cnt)
-        plan.timing_enable(False)
-    # one reference step for the FP32/FP64 comparison
-    phi, F, E, modes = plan.rbm_step(pos, q, P_MODES, seed=1, step=0)
-    torch.cuda.synchronize()
-    out = dict(ms_per_step=(t1 - t0) * 1e3 / steps, timers=timers,
-               F=F.double().cpu().numpy(), modes=modes.cpu().numpy())
-    plan.close()
+    return (t1 - t0) * 1e3 / steps
+
+
+def read_timers(plan):
+    import paper_2403_01521_amd as q2d
+    out = {}
+    for name, idx in (("sweep", q2d.TIMER_SWEEP), ("agg", q2d.TIMER_AGG),
+                      ("sort", q2d.TIMER_SORT), ("k0", q2d.TIMER_K0), ("call", q2d.TIMER_CALL)):
+        out[name] = plan.timing_read(idx)
+    plan.timing_enable(0)
     return out
+
+
+def half_lattice(m, wt):
+    """k and -k give equal contributions: keep one of each pair, doubled weight."""
+    keep = (m[:, 0] > 0) | ((m[:, 0] == 0) & (m[:, 1] > 0))
+    return m[keep], 2.0 * wt[keep]
 
 
 def cpu_baseline(c, w, s, modes):
     """The oracle's O(N) recursion (plain C, FP64), one thread, all particles,
-    the first P_s of the step's modes; scaled to the full batch."""
+    the first P_s of the step's modes; scaled to the full batch.  Also on all
+    host threads, and the direct pair sums (O2) on a few targets, scaled to
+    N targets (the plain O(N^2)-per-mode cost)."""
     from oracle import lattice, soewald2d
     from oracle import recursion as o3
     o3.build()
     box, alpha = c["box"], c["alpha"]
     H = lattice.H_direct(box[0], box[1], alpha)
-    Ps = 10
-    wt = soewald2d.rb_weights(P_MODES, H, box[0], box[1])[:Ps]
+    wt = soewald2d.rb_weights(P_MODES, H, box[0], box[1])
     pos = c["pos"].astype(np.float64)
     q = c["q"].astype(np.float64)
+    N = len(q)
+    Ps = 10
     t0 = time.perf_counter()
-    o3.long_range(pos, q, box, alpha, w, s, modes[:Ps], wt, include_self_pair=False, diag=0.0,
-                  nthreads=1)
-    t = time.perf_counter() - t0
-    t_full = t * P_MODES / Ps
-    return dict(value=len(q) / t_full, unit="particle-force evals/s", cores=1, kind="oracle",
+    o3.long_range(pos, q, box, alpha, w, s, modes[:Ps], wt[:Ps], include_self_pair=False,
+                  diag=0.0, nthreads=1)
+    t1 = time.perf_counter() - t0
+    nthr = os.cpu_count() or 1
+    Pa = 40
+    t0 = time.perf_counter()
+    o3.long_range(pos, q, box, alpha, w, s, modes[:Pa], wt[:Pa], include_self_pair=False,
+                  diag=0.0, nthreads=0)
+    ta = time.perf_counter() - t0
+    tg, Po = 2, 5
+    t0 = time.perf_counter()
+    soewald2d.long_range(pos, q, box, alpha, w, s, modes[:Po], wt[:Po],
+                         targets=np.arange(tg), include_self_pair=False, diag=0.0)
+    to = time.perf_counter() - t0
+    return dict(value=N / (t1 * P_MODES / Ps), unit="particle-force evals/s", cores=1,
+                kind="oracle",
                 sample="O3 FP64 recursion over all %d particles for %d of the %d modes "
-                       "(%.1f s), scaled by %d/%d" % (len(q), Ps, P_MODES, t, P_MODES, Ps),
-                host_cpu=_cpu_model(), host_threads=os.cpu_count())
+                       "(%.1f s), scaled by %d/%d" % (N, Ps, P_MODES, t1, P_MODES, Ps),
+                all_threads=dict(value=N / (ta * P_MODES / Pa), threads=nthr,
+                                 sample="O3, OpenMP over modes, %d of %d modes (%.1f s)"
+                                        % (Pa, P_MODES, ta)),
+                direct_pairs_o2=dict(value=N / (to * (N / tg) * (P_MODES / Po)), threads=1,
+                                     sample="O2 direct pair sums (numpy) for %d targets x %d "
+                                            "modes (%.1f s), scaled to %d targets x %d modes"
+                                            % (tg, Po, to, N, P_MODES)),
+                host_cpu=_cpu_model(), host_threads=nthr)
 
 
 def _cpu_model():
@@ -151,10 +188,12 @@ def calibrate_copy():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the FP64 exact-k reference (time and random-batch error)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -169,17 +208,29 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    import paper_2403_01521_amd as q2d
     import workloads as wl
     w, s = soe_table(M_SOE)
     c32 = wl.make_config(3, dtype=np.float32)
+    box, alpha = c32["box"], c32["alpha"]
     N = len(c32["q"])
-    r32 = run_gpu("fp32", c32, w, s, args.steps, args.warmup, timing=True)
-    ms = r32["ms_per_step"]
+    pos32 = torch.tensor(c32["pos"], device="cuda")
+    q32 = torch.tensor(c32["q"], device="cuda")
+    plan32 = q2d.Plan(box, alpha, w, s, precision="fp32", n_max=N, p_max=P_MODES)
+
+    # timed steps: only the sweep's events
+    log("FP32 random-batch steps: %d warm-up + %d timed" % (args.warmup, args.steps))
+    ms = time_steps(plan32, pos32, q32, args.steps, args.warmup, 1 << q2d.TIMER_SWEEP)
+    sw_ms, sw_cnt = read_timers(plan32)["sweep"]
+    # breakdown: a separate pass with every timer
+    nb = min(args.steps, 20)
+    time_steps(plan32, pos32, q32, nb, 0, q2d.TIMING_ALL)
+    brk = read_timers(plan32)
+
     fl = flops_per_mode_particle(M_SOE) * P_MODES * N
-    # the sweep runs as several launches per step (whole 64-mode groups, then
-    # power-of-two bands of the remaining modes): FLOP of all of them over
-    # their summed time, i.e. average FLOP per launch over average duration
-    sw_ms, sw_cnt = r32["timers"]["sweep"]
+    # the sweep runs as one launch per step covering all modes (a 64-mode group
+    # and power-of-two bands of the rest): average FLOP per launch over average
+    # duration
     per_step = max(sw_cnt, 1) / args.steps
     sweep_ms = sw_ms / max(sw_cnt, 1)
     achieved = fl / (sw_ms / args.steps * 1e-3) / 1e12
@@ -199,28 +250,90 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rbm_step N=1e6 slab 600x600x10 surface-excess, alpha=0.1, "
                                "P=100, M=16, FP32 scans (FP64 k=0, carries, energy)",
-                   "N": N, "P": P_MODES, "M": M_SOE, "alpha": 0.1, "box": [600, 600, 10]},
+                   "N": N, "P": P_MODES, "M": M_SOE, "alpha": alpha, "box": list(box)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": traffic_from_profile(scan_src),
                      "kernel": "k_sweep<float,8>", "flop_per_launch": fl / per_step,
                      "launch_ms": sweep_ms, "launches_per_step": per_step},
-        "step_breakdown_ms": {k: v[0] / args.steps for k, v in r32["timers"].items()},
+        "step_breakdown_ms": {k: v[0] / nb for k, v in brk.items()},
         "step_flop_frac": fl / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
     }
+
+    # random-batch force error against the full k-sum (FP64 exact-k SOE over
+    # every mode with e^{-k^2/4 alpha^2} >= 1e-16), per draw and running mean,
+    # for the K timed draws (same seeds)
+    if not args.no_exact:
+        log("FP64 exact-k reference and random-batch error over %d draws" % args.steps)
+        from oracle import soewald2d
+        kc = 2 * alpha * np.sqrt(np.log(1e16))
+        pos64 = pos32.double()
+        q64 = q32.double()
+        plan_ex = q2d.Plan(box, alpha, w, s, kc=kc, precision="fp64", n_max=N)
+        n_modes = plan_ex.info()["n_modes_exact"]
+        plan_ex.long_range(pos64, q64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, F_ref, E_ref = plan_ex.long_range(pos64, q64)
+        torch.cuda.synchronize()
+        t_ex = time.perf_counter() - t0
+        # the k != 0 part of the reference force (the j = i constant carries none)
+        m_all, wt_all = soewald2d.exact_modes(box[0], box[1], alpha, kc)
+        mh, wh = half_lattice(m_all, wt_all)
+        _, F_ref_k, _ = plan_ex.modes_eval(pos64, q64,
+                                           torch.tensor(mh, dtype=torch.int32, device="cuda"),
+                                           torch.tensor(wh, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        plan_ex.close()
+        per_draw = []
+        run = torch.zeros_like(F_ref)
+        run_err = {}
+        for i in range(args.steps):
+            _, F, _, _ = plan32.rbm_step(pos32, q32, P_MODES, seed=SEED, step=i)
+            Fd = F.double()
+            per_draw.append(rel(Fd, F_ref))
+            run += Fd
+            n = i + 1
+            if n in (1, 10, 100, args.steps):
+                run_err[str(n)] = rel(run / n, F_ref)
+        nrm = float(torch.linalg.norm(F_ref))
+        nrm_k = float(torch.linalg.norm(F_ref_k))
+        res["exact_k_fp64"] = {
+            "modes": len(m_all), "half_lattice_modes_computed": int(n_modes),
+            "ms": t_ex * 1e3, "evals_per_s": N / t_ex,
+            "note": "all k with e^{-k^2/4a^2} >= 1e-16 (k_c = %.4f), FP64, same GPU" % kc}
+        res["rb_force_error_vs_full_k"] = {
+            "per_draw_rel_rms_mean": float(np.mean(per_draw)),
+            "per_draw_rel_rms_max": float(np.max(per_draw)),
+            "running_mean_rel_rms": run_err,
+            "k_nonzero_part_share": nrm_k / nrm,
+            "per_draw_rel_to_k_nonzero_part": float(np.mean(per_draw)) * nrm / nrm_k,
+            "draws": args.steps,
+            "note": "relative RMS over all particles of F_RB(FP32) - F_exact(FP64); the "
+                    "k = 0 part is exact in both, so the error is the k != 0 sampling "
+                    "error (also given relative to the k != 0 part's norm)"}
+
+    _, F32, _, m32 = plan32.rbm_step(pos32, q32, P_MODES, seed=SEED, step=0)
+    torch.cuda.synchronize()
+    r32_modes = m32.cpu().numpy()
+    plan32.close()
     if not args.no_fp64:
-        c64 = dict(c32)
-        c64["pos"] = c32["pos"].astype(np.float64)
-        c64["q"] = c32["q"].astype(np.float64)
-        r64 = run_gpu("fp64", c64, w, s, max(3, args.steps // 4), 2, timing=False)
-        res["fp64_ms_per_step"] = r64["ms_per_step"]
-        res["fp64_value"] = N / (r64["ms_per_step"] * 1e-3)
-        res["fp32_over_fp64_speedup"] = r64["ms_per_step"] / ms
-        assert np.array_equal(r64["modes"], r32["modes"])
-        d = r32["F"] - r64["F"]
-        res["fp32_vs_fp64_force_rel_rms"] = float(np.linalg.norm(d) / np.linalg.norm(r64["F"]))
+        log("FP64 random-batch steps")
+        pos64 = pos32.double()
+        q64 = q32.double()
+        plan64 = q2d.Plan(box, alpha, w, s, precision="fp64", n_max=N, p_max=P_MODES)
+        ms64 = time_steps(plan64, pos64, q64, max(10, args.steps // 4), 3, 0)
+        _, F64, _, m64 = plan64.rbm_step(pos64, q64, P_MODES, seed=SEED, step=0)
+        torch.cuda.synchronize()
+        plan64.close()
+        assert np.array_equal(m64.cpu().numpy(), r32_modes)
+        res["fp64_ms_per_step"] = ms64
+        res["fp64_value"] = N / (ms64 * 1e-3)
+        res["fp32_over_fp64_speedup"] = ms64 / ms
+        res["fp32_vs_fp64_force_rel_rms"] = rel(F32.double(), F64)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(c32, w, s, r32["modes"])
+        log("oracle timing on the host")
+        res["cpu_baseline"] = cpu_baseline(c32, w, s, r32_modes)
     print(json.dumps(res))
 
 

@@ -133,6 +133,24 @@ q2d_status q2d_rbm_step(q2d_plan_t plan, const void *pos, const void *q, int64_t
                         int32_t *modes_out);
 
 /*
+ * q2d_modes_eval -- the k != 0 Fourier sum over a caller-given list of modes
+ * with caller-given weights (the terms of eq. SOEphi with the forces of
+ * App. E, term by term): for each listed mode k with weight omega_k,
+ *   phi_i += omega_k sum_{j != i} q_j Re e^{i k.(rho_i - rho_j)} K_k(|z_i - z_j|)
+ * (the pair kernel K_k of the SOE, its Gaussian factor being part of omega_k),
+ * F_i = -grad_i of E, E = 1/2 sum_i q_i phi_i.  No k = 0 term, no j = i term
+ * and no self term: with omega_k = (pi/A) e^{-k^2/(4 alpha^2)} over a subset of
+ * the lattice this is that subset's part of q2d_long_range minus its j = i
+ * constant; with omega_k = (pi/A) H/P over sampled modes, the k != 0 pair part
+ * of q2d_rbm_step.  modes: device int32 array n_modes x 2 (mx, my), k =
+ * 2 pi (mx/Lx, my/Ly), a (0, 0) entry adds nothing; weights: device double
+ * array n_modes.  Scratch for the list is allocated on first use and grows.
+ */
+q2d_status q2d_modes_eval(q2d_plan_t plan, const void *pos, const void *q, int64_t N,
+                          const int32_t *modes, const double *weights, int64_t n_modes, void *phi,
+                          void *F, double *E);
+
+/*
  * q2d_short_range -- real-space part phi_s (eq. phi_s) with cutoff r_c by a
  * uniform cell list: phi_i = sum over images m and j (j != i when m = 0) with
  * |r_ij + M| <= r_c of q_j erfc(alpha r)/r, the matching force and
@@ -159,14 +177,17 @@ q2d_status q2d_plan_check(q2d_plan_t plan);
 q2d_status q2d_soe_fit(int32_t M, double *w, double *s, double *sup_err);
 
 /*
- * Kernel timing (measurement only): when enabled, the plan records HIP events
- * around the launches of one kernel family on its stream and accumulates
- * their elapsed time.  which: 0 = k != 0 sweep (the hot kernel), 1 = k != 0
- * aggregate pass, 2 = z-sort, 3 = k = 0 term, 4 = whole call.
- * q2d_plan_timing_read synchronises and returns total milliseconds and the
- * number of launches measured since the last reset (enable resets).
+ * Kernel timing (measurement only): the plan records HIP events around the
+ * launches of the selected kernel families on the stream they run on and
+ * accumulates their elapsed time.  Families: 0 = k != 0 sweep (the hot
+ * kernel), 1 = k != 0 aggregate pass, 2 = z-sort, 3 = k = 0 term (internal
+ * stream), 4 = whole call.  mask: bit w selects family w (0 disables; 31 =
+ * all).  Every recorded event can delay the next launch by a few
+ * microseconds, so time only what is needed.  q2d_plan_timing_read
+ * synchronises and returns total milliseconds and the number of launches
+ * measured since the last reset (enable resets).
  */
-q2d_status q2d_plan_timing_enable(q2d_plan_t plan, int32_t enable);
+q2d_status q2d_plan_timing_enable(q2d_plan_t plan, int32_t mask);
 q2d_status q2d_plan_timing_read(q2d_plan_t plan, int32_t which, double *ms_total, int64_t *count);
 
 /* Static description of a status code. */

@@ -29,9 +29,11 @@ STATUS = {
 }
 FP64, FP32 = 0, 1
 TIMER_SWEEP, TIMER_AGG, TIMER_SORT, TIMER_K0, TIMER_CALL = 0, 1, 2, 3, 4
+TIMING_ALL = 31
 
 EXPORTS = ("q2d_plan_create", "q2d_plan_destroy", "q2d_plan_set_stream", "q2d_plan_info",
-           "q2d_long_range", "q2d_rbm_step", "q2d_short_range", "q2d_plan_check",
+           "q2d_long_range", "q2d_rbm_step", "q2d_modes_eval", "q2d_short_range",
+           "q2d_plan_check",
            "q2d_soe_fit", "q2d_plan_timing_enable", "q2d_plan_timing_read",
            "q2d_status_string")
 
@@ -76,6 +78,7 @@ def load_library(path=None):
     lib.q2d_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.q2d_long_range.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     lib.q2d_rbm_step.argtypes = [vp, vp, vp, i64, i32, u64, u64, vp, vp, vp, vp]
+    lib.q2d_modes_eval.argtypes = [vp, vp, vp, i64, vp, vp, i64, vp, vp, vp]
     lib.q2d_short_range.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     lib.q2d_plan_check.argtypes = [vp]
     lib.q2d_soe_fit.argtypes = [i32, dp, dp, dp]
@@ -209,6 +212,24 @@ class Plan:
                                       modes.data_ptr()), "q2d_rbm_step")
         return phi, F, E, modes
 
+    def modes_eval(self, pos, q, modes, weights):
+        """k != 0 sum over the given modes ((n, 2) int32 device tensor) with the
+        given weights ((n,) float64 device tensor): (phi, F, E) device tensors."""
+        self._sync_stream()
+        pos, q, n, phi, F, E = self._prep(pos, q)
+        t = self._torch
+        if not (modes.is_cuda and weights.is_cuda):
+            raise ValueError("modes and weights must be device tensors")
+        modes = modes.to(t.int32).contiguous()
+        weights = weights.to(t.float64).contiguous()
+        if modes.dim() != 2 or modes.shape[1] != 2 or weights.shape != (modes.shape[0],):
+            raise ValueError("modes must be (n, 2) and weights (n,)")
+        _check(self._lib.q2d_modes_eval(self._h, pos.data_ptr(), q.data_ptr(), n,
+                                        modes.data_ptr(), weights.data_ptr(), modes.shape[0],
+                                        phi.data_ptr(), F.data_ptr(), E.data_ptr()),
+               "q2d_modes_eval")
+        return phi, F, E
+
     def short_range(self, pos, q):
         """Real-space erfc sum with cutoff rc: (phi, F, E) device tensors."""
         self._sync_stream()
@@ -222,8 +243,11 @@ class Plan:
         """Wait for the stream; return the device-side data status code (0 = ok)."""
         return int(self._lib.q2d_plan_check(self._h))
 
-    def timing_enable(self, on=True):
-        _check(self._lib.q2d_plan_timing_enable(self._h, 1 if on else 0), "timing_enable")
+    def timing_enable(self, mask=TIMING_ALL):
+        """Select timed kernel families (bit TIMER_x); True = all, False/0 = none."""
+        if mask is True:
+            mask = TIMING_ALL
+        _check(self._lib.q2d_plan_timing_enable(self._h, int(mask)), "timing_enable")
 
     def timing_read(self, which):
         ms = ctypes.c_double(0.0)

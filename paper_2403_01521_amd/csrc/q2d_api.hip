@@ -41,7 +41,7 @@ q2d_status ensure(Plan *p, Buf &b, size_t bytes) {
 }
 
 void tstart(Plan *p, int which) {
-    if (!p->timing) return;
+    if (!(p->timing & (1 << which))) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     (void)hipEventRecord(e, p->stream);
@@ -49,7 +49,7 @@ void tstart(Plan *p, int which) {
 }
 
 void tstop(Plan *p, int which) {
-    if (!p->timing) return;
+    if (!(p->timing & (1 << which))) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     (void)hipEventRecord(e, p->stream);
@@ -144,6 +144,28 @@ __global__ void k_zero_status(int *st, double *qs) {
     st[0] = 0;
     qs[0] = 0.0;
     qs[1] = 0.0;
+}
+
+// caller's (mx, my) pairs and weights -> the [2][n_pad] mode table; a (0, 0)
+// entry (no k != 0 mode) becomes (1, 0) with weight 0 so that it adds nothing
+__global__ void k_user_modes(const int32_t *in, const double *w_in, int64_t n, int64_t n_pad,
+                             int32_t *modes, double *w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    int32_t mx = 0, my = 0;
+    double wt = 0.0;
+    if (i < n) {
+        mx = in[2 * i];
+        my = in[2 * i + 1];
+        wt = w_in[i];
+    }
+    if (mx == 0 && my == 0) {
+        mx = 1;
+        wt = 0.0;
+    }
+    modes[i] = mx;
+    modes[n_pad + i] = my;
+    w[i] = wt;
 }
 
 __global__ void k_modes_out(const int32_t *modes, int P, int p_pad, int32_t *out) {
@@ -449,7 +471,7 @@ q2d_status q2d_plan_destroy(q2d_plan_t p) {
         p->pend_ev[w].clear();
     }
     Buf *bufs[] = {&p->exact_modes, &p->exact_coef, &p->rb_modes, &p->rb_coef, &p->rb_work,
-                   &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
+                   &p->user_modes, &p->user_w, &p->user_coef, &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
                    &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->carry_tmp, &p->outk, &p->spans0,
                    &p->agg0, &p->carry_tmp0, &p->phi0, &p->fz0, &p->epart, &p->status,
                    &p->cell_start, &p->cell_count, &p->cell_idx, &p->cell_tmp};
@@ -503,7 +525,7 @@ q2d_status q2d_long_range(q2d_plan_t p, const void *pos, const void *q, int64_t 
             return st;
         if (hipStreamWaitEvent(p->stream, p->ev_k0, 0) != hipSuccess) return Q2D_EDEVICE;
     }
-    st = epilogue(p, N, nch, p->diag_exact, q, phi, F, E);
+    st = epilogue(p, N, nch, p->diag_exact, true, phi, F, E);
     tstop(p, 4);
     return st;
 }
@@ -542,7 +564,40 @@ q2d_status q2d_rbm_step(q2d_plan_t p, const void *pos, const void *q, int64_t N,
     } else if (hipStreamWaitEvent(p->stream, p->ev_modes, 0) != hipSuccess) {
         return Q2D_EDEVICE;
     }
-    st = epilogue(p, N, nch, p->diag_rb, q, phi, F, E);
+    st = epilogue(p, N, nch, p->diag_rb, true, phi, F, E);
+    tstop(p, 4);
+    return st;
+}
+
+q2d_status q2d_modes_eval(q2d_plan_t p, const void *pos, const void *q, int64_t N,
+                          const int32_t *modes, const double *weights, int64_t n_modes, void *phi,
+                          void *F, double *E) {
+    q2d_status st = check_io(p, pos, q, N);
+    if (st != Q2D_OK) return st;
+    if (n_modes < 0 || (n_modes > 0 && (!modes || !weights)) || n_modes > ((int64_t)1 << 30))
+        return Q2D_EINVAL;
+    tstart(p, 4);
+    int nch = 0;
+    if (N > 0 && n_modes > 0) {
+        const int64_t n_pad = ((n_modes + WAVE - 1) / WAVE) * WAVE;
+        const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+        if ((st = ensure(p, p->user_modes, (size_t)2 * n_pad * sizeof(int32_t))) != Q2D_OK ||
+            (st = ensure(p, p->user_w, (size_t)n_pad * sizeof(double))) != Q2D_OK ||
+            (st = ensure(p, p->user_coef, (size_t)coef_fields(p->mh) * n_pad * tsz)) != Q2D_OK)
+            return st;
+        k_user_modes<<<(int)((n_pad + 255) / 256), 256, 0, p->stream>>>(
+            modes, weights, n_modes, n_pad, (int32_t *)p->user_modes.p, (double *)p->user_w.p);
+        if ((st = build_mode_coefs(p, (const int32_t *)p->user_modes.p, n_modes, n_pad,
+                                   (const double *)p->user_w.p, 0.0, p->user_coef.p)) != Q2D_OK)
+            return st;
+        if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
+        if ((st = kmodes_run(p, N, (const int32_t *)p->user_modes.p, p->user_coef.p, n_pad, 0,
+                             n_modes, &nch)) != Q2D_OK)
+            return st;
+    } else if (N > 0) {
+        if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
+    }
+    st = epilogue(p, N, nch, 0.0, false, phi, F, E);
     tstop(p, 4);
     return st;
 }
@@ -552,7 +607,7 @@ q2d_status q2d_short_range(q2d_plan_t p, const void *pos, const void *q, int64_t
     q2d_status st = check_io(p, pos, q, N);
     if (st != Q2D_OK) return st;
     if (!(p->rc > 0)) return Q2D_EUNSUPPORTED;
-    if (N == 0) return epilogue(p, 0, 0, 0.0, q, nullptr, nullptr, E);
+    if (N == 0) return epilogue(p, 0, 0, 0.0, true, nullptr, nullptr, E);
     return short_range_run(p, pos, q, N, phi, F, E);
 }
 
@@ -568,14 +623,14 @@ q2d_status q2d_plan_check(q2d_plan_t p) {
     return (q2d_status)first_error(bits);
 }
 
-q2d_status q2d_plan_timing_enable(q2d_plan_t p, int32_t enable) {
+q2d_status q2d_plan_timing_enable(q2d_plan_t p, int32_t mask) {
     if (!p) return Q2D_EINVAL;
     timing_flush(p);
     for (int w = 0; w < 5; ++w) {
         p->t_ms[w] = 0;
         p->t_cnt[w] = 0;
     }
-    p->timing = enable != 0;
+    p->timing = mask & 31;
     return Q2D_OK;
 }
 

@@ -1,6 +1,7 @@
 // Epilogue: sum the parts of the long-range potential and force in sorted
 // order, scatter them back to input order, and reduce the energy in FP64.
 //   phi_i = sum_k phi^k_i + q_i D + phi^0_i - 2 alpha q_i / sqrt(pi)   (Sec. 2.2, eq. self)
+// (the k = 0 and self terms are left out for a partial k-space sum)
 //   F_i   = q_i (sum_k force parts) + F^0_i
 //   E     = 1/2 sum_i q_i phi_i                                        (pair energy, Sec. 2.1)
 // D is the configuration-independent j = i constant of the k != 0 modes.
@@ -36,13 +37,13 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epi(int64_t N, int nchunks,
             o3 += (double)o[3];
         }
         const double q = (double)qs[i];
-        const double ph = o0 + q * diag + phi0[i] - self_c * q;
+        const double ph = o0 + q * diag + (phi0 ? phi0[i] : 0.0) - self_c * q;
         const int64_t orig = perm[i];
         if (phi) phi[orig] = (T)ph;
         if (F) {
             F[3 * orig] = (T)(q * o1);
             F[3 * orig + 1] = (T)(q * o2);
-            F[3 * orig + 2] = (T)(q * o3 + fz0[i]);
+            F[3 * orig + 2] = (T)(q * o3 + (fz0 ? fz0[i] : 0.0));
         }
         e = q * ph;
     }
@@ -73,9 +74,8 @@ __global__ void k_set_zero(double *E) { E[0] = 0.0; }
 
 }  // namespace
 
-q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, const void *q, void *phi,
+q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0, void *phi,
                     void *F, double *E) {
-    (void)q;
     if (N <= 0) {
         if (E) k_set_zero<<<1, 1, 0, p->stream>>>(E);
         return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
@@ -83,16 +83,18 @@ q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, const void *q
     const int nb = (int)((N + EPI_THREADS - 1) / EPI_THREADS);
     q2d_status st;
     if ((st = ensure(p, p->epart, (size_t)nb * sizeof(double))) != Q2D_OK) return st;
-    const double self_c = 2.0 * p->alpha / sqrt(3.14159265358979323846);
+    const double self_c = with_k0 ? 2.0 * p->alpha / sqrt(3.14159265358979323846) : 0.0;
+    const double *phi0 = with_k0 ? (const double *)p->phi0.p : nullptr;
+    const double *fz0 = with_k0 ? (const double *)p->fz0.p : nullptr;
     if (p->fp32)
         k_epi<float><<<nb, EPI_THREADS, 0, p->stream>>>(
-            N, n_chunks, (const float *)p->outk.p, (const float *)p->s_q.p,
-            (const double *)p->phi0.p, (const double *)p->fz0.p, p->perm, diag, self_c,
+            N, n_chunks, (const float *)p->outk.p, (const float *)p->s_q.p, phi0, fz0, p->perm,
+            diag, self_c,
             (float *)phi, (float *)F, (double *)p->epart.p);
     else
         k_epi<double><<<nb, EPI_THREADS, 0, p->stream>>>(
-            N, n_chunks, (const double *)p->outk.p, (const double *)p->s_q.p,
-            (const double *)p->phi0.p, (const double *)p->fz0.p, p->perm, diag, self_c,
+            N, n_chunks, (const double *)p->outk.p, (const double *)p->s_q.p, phi0, fz0, p->perm,
+            diag, self_c,
             (double *)phi, (double *)F, (double *)p->epart.p);
     if (E) k_energy<<<1, EPI_THREADS, 0, p->stream>>>((const double *)p->epart.p, nb, E);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;

@@ -79,6 +79,11 @@ struct Plan {
     Buf exact_modes;  // int32 [2][n_exact_pad]
     Buf exact_coef;   // T [fields][n_exact_pad]
 
+    // caller-given mode list (q2d_modes_eval)
+    Buf user_modes;   // int32 [2][n_pad]
+    Buf user_w;       // double [n_pad]
+    Buf user_coef;    // T [fields][n_pad]
+
     // random-batch tables
     Buf rb_modes;     // int32 [2][p_pad]
     Buf rb_coef;      // T [fields][p_pad]
@@ -107,7 +112,7 @@ struct Plan {
     Buf cell_start, cell_count, cell_idx, cell_tmp;
 
     // timing
-    bool timing = false;
+    int timing = 0;  // bit mask of timed kernel families
     hipEvent_t ev[5][2]{};
     double t_ms[5]{};
     int64_t t_cnt[5]{};
@@ -143,7 +148,7 @@ q2d_status kmodes_run(Plan *p, int64_t N, const int32_t *modes, const void *coef
 q2d_status k0_run(Plan *p, int64_t N);
 
 // combine, unsort, energy
-q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, const void *q, void *phi,
+q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0, void *phi,
                     void *F, double *E);
 
 // short range
