@@ -133,6 +133,27 @@ q2d_status q2d_rbm_step(q2d_plan_t plan, const void *pos, const void *q, int64_t
                         int32_t *modes_out);
 
 /*
+ * Adjoint (vector-Jacobian product) of the potential of q2d_long_range /
+ * q2d_rbm_step.  For weights g_i on the outputs phi_i (L = sum_i g_i phi_i):
+ *   dq_j   = dL/dq_j   = sum_i g_i G(r_i, r_j) = the potential of "charges" g at r_j,
+ *   dpos_k = dL/dr_k   = -(g_k f(q)_k + q_k f(g)_k),
+ * where phi_i = sum_j G(r_i, r_j) q_j (the same Fourier sums, j = i, k = 0 and
+ * self terms as the forward call; G is symmetric) and f(s)_k is the field of
+ * sources s at r_k (the force on a unit charge, App. E).  For the energy
+ * E = 1/2 sum q_i phi_i no second pass is needed: dE/dq = phi and dE/dpos = -F
+ * (dpos with g = q/2).  The scans
+ * run twice, with sources q and with sources g (g need not be neutral; the
+ * data checks apply to q only).  g: device array N (plan dtype); dq (N),
+ * dpos (N x 3): device outputs or NULL.  The random-batch form uses the modes
+ * of (seed, step), i.e. the same estimator as q2d_rbm_step.
+ */
+q2d_status q2d_long_range_vjp(q2d_plan_t plan, const void *pos, const void *q, const void *g,
+                              int64_t N, void *dq, void *dpos);
+q2d_status q2d_rbm_step_vjp(q2d_plan_t plan, const void *pos, const void *q, const void *g,
+                            int64_t N, int32_t P, uint64_t seed, uint64_t step, void *dq,
+                            void *dpos);
+
+/*
  * q2d_modes_eval -- the k != 0 Fourier sum over a caller-given list of modes
  * with caller-given weights (the terms of eq. SOEphi with the forces of
  * App. E, term by term): for each listed mode k with weight omega_k,

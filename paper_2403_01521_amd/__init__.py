@@ -32,7 +32,8 @@ TIMER_SWEEP, TIMER_AGG, TIMER_SORT, TIMER_K0, TIMER_CALL = 0, 1, 2, 3, 4
 TIMING_ALL = 31
 
 EXPORTS = ("q2d_plan_create", "q2d_plan_destroy", "q2d_plan_set_stream", "q2d_plan_info",
-           "q2d_long_range", "q2d_rbm_step", "q2d_modes_eval", "q2d_short_range",
+           "q2d_long_range", "q2d_rbm_step", "q2d_long_range_vjp", "q2d_rbm_step_vjp",
+           "q2d_modes_eval", "q2d_short_range",
            "q2d_plan_check",
            "q2d_soe_fit", "q2d_plan_timing_enable", "q2d_plan_timing_read",
            "q2d_status_string")
@@ -78,6 +79,8 @@ def load_library(path=None):
     lib.q2d_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.q2d_long_range.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     lib.q2d_rbm_step.argtypes = [vp, vp, vp, i64, i32, u64, u64, vp, vp, vp, vp]
+    lib.q2d_long_range_vjp.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    lib.q2d_rbm_step_vjp.argtypes = [vp, vp, vp, vp, i64, i32, u64, u64, vp, vp]
     lib.q2d_modes_eval.argtypes = [vp, vp, vp, i64, vp, vp, i64, vp, vp, vp]
     lib.q2d_short_range.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     lib.q2d_plan_check.argtypes = [vp]
@@ -211,6 +214,35 @@ class Plan:
                                       phi.data_ptr(), F.data_ptr(), E.data_ptr(),
                                       modes.data_ptr()), "q2d_rbm_step")
         return phi, F, E, modes
+
+    def _prep_vjp(self, pos, q, g):
+        pos, q, n, _, _, _ = self._prep(pos, q)
+        if not g.is_cuda or g.dtype != self.dtype or g.shape != (n,):
+            raise ValueError("g must be a device tensor of shape (N,) and the plan's dtype")
+        g = g.contiguous()
+        t = self._torch
+        dq = t.empty(n, dtype=self.dtype, device=pos.device)
+        dpos = t.empty((n, 3), dtype=self.dtype, device=pos.device)
+        return pos, q, g, n, dq, dpos
+
+    def long_range_vjp(self, pos, q, g):
+        """Adjoint of long_range's potential for weights g: (dq, dpos) device tensors."""
+        self._sync_stream()
+        pos, q, g, n, dq, dpos = self._prep_vjp(pos, q, g)
+        _check(self._lib.q2d_long_range_vjp(self._h, pos.data_ptr(), q.data_ptr(), g.data_ptr(),
+                                            n, dq.data_ptr(), dpos.data_ptr()),
+               "q2d_long_range_vjp")
+        return dq, dpos
+
+    def rbm_step_vjp(self, pos, q, g, P, seed, step):
+        """Adjoint of rbm_step's potential (same modes for the same seed, step)."""
+        self._sync_stream()
+        pos, q, g, n, dq, dpos = self._prep_vjp(pos, q, g)
+        _check(self._lib.q2d_rbm_step_vjp(self._h, pos.data_ptr(), q.data_ptr(), g.data_ptr(), n,
+                                          int(P), ctypes.c_uint64(seed), ctypes.c_uint64(step),
+                                          dq.data_ptr(), dpos.data_ptr()),
+               "q2d_rbm_step_vjp")
+        return dq, dpos
 
     def modes_eval(self, pos, q, modes, weights):
         """k != 0 sum over the given modes ((n, 2) int32 device tensor) with the

@@ -199,6 +199,30 @@ q2d_status k0_side(Plan *p, int64_t N) {
     return hipEventRecord(p->ev_k0, p->side) == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
+// The two passes of the adjoint once the particles are sorted (and, for the
+// random batch, the modes drawn): sources q keep their field in p->fq, then
+// sources g give phi(g) and f(g), combined by the adjoint epilogue.
+q2d_status vjp_passes(Plan *p, int64_t N, const int32_t *modes, const void *coef,
+                      int64_t stride, int64_t n_modes, double diag, const void *g, void *dq,
+                      void *dpos) {
+    q2d_status st;
+    int nch = 0;
+    p->src = nullptr;
+    if ((st = k0_side(p, N)) != Q2D_OK) return st;
+    if (n_modes > 0 && (st = kmodes_run(p, N, modes, coef, stride, 0, n_modes, &nch)) != Q2D_OK)
+        return st;
+    if (hipStreamWaitEvent(p->stream, p->ev_k0, 0) != hipSuccess) return Q2D_EDEVICE;
+    if ((st = epilogue_field(p, N, nch)) != Q2D_OK) return st;
+    if ((st = gather_sources(p, g, N)) != Q2D_OK) return st;
+    p->src = p->s_g.p;
+    st = k0_side(p, N);
+    if (st == Q2D_OK && n_modes > 0) st = kmodes_run(p, N, modes, coef, stride, 0, n_modes, &nch);
+    p->src = nullptr;
+    if (st != Q2D_OK) return st;
+    if (hipStreamWaitEvent(p->stream, p->ev_k0, 0) != hipSuccess) return Q2D_EDEVICE;
+    return epilogue_vjp(p, N, nch, diag, dq, dpos);
+}
+
 }  // namespace
 
 extern "C" {
@@ -471,7 +495,8 @@ q2d_status q2d_plan_destroy(q2d_plan_t p) {
         p->pend_ev[w].clear();
     }
     Buf *bufs[] = {&p->exact_modes, &p->exact_coef, &p->rb_modes, &p->rb_coef, &p->rb_work,
-                   &p->user_modes, &p->user_w, &p->user_coef, &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
+                   &p->user_modes, &p->user_w, &p->user_coef, &p->s_g, &p->fq,
+                   &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
                    &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->carry_tmp, &p->outk, &p->spans0,
                    &p->agg0, &p->carry_tmp0, &p->phi0, &p->fz0, &p->epart, &p->status,
                    &p->cell_start, &p->cell_count, &p->cell_idx, &p->cell_tmp};
@@ -565,6 +590,49 @@ q2d_status q2d_rbm_step(q2d_plan_t p, const void *pos, const void *q, int64_t N,
         return Q2D_EDEVICE;
     }
     st = epilogue(p, N, nch, p->diag_rb, true, phi, F, E);
+    tstop(p, 4);
+    return st;
+}
+
+q2d_status q2d_long_range_vjp(q2d_plan_t p, const void *pos, const void *q, const void *g,
+                              int64_t N, void *dq, void *dpos) {
+    q2d_status st = check_io(p, pos, q, N);
+    if (st != Q2D_OK) return st;
+    if (N > 0 && !g) return Q2D_EINVAL;
+    if (!(p->kc > 0)) return Q2D_EUNSUPPORTED;
+    if (N == 0) return Q2D_OK;
+    tstart(p, 4);
+    if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
+    st = vjp_passes(p, N, (const int32_t *)p->exact_modes.p, p->exact_coef.p, p->n_exact_pad,
+                    p->n_exact, p->diag_exact, g, dq, dpos);
+    tstop(p, 4);
+    return st;
+}
+
+q2d_status q2d_rbm_step_vjp(q2d_plan_t p, const void *pos, const void *q, const void *g,
+                            int64_t N, int32_t P, uint64_t seed, uint64_t step, void *dq,
+                            void *dpos) {
+    q2d_status st = check_io(p, pos, q, N);
+    if (st != Q2D_OK) return st;
+    if (N > 0 && !g) return Q2D_EINVAL;
+    if (P < 1) return Q2D_EINVAL;
+    if (p->opts.p_max <= 0) return Q2D_EUNSUPPORTED;
+    if (P > p->opts.p_max) return Q2D_ECAPACITY;
+    if (N == 0) return Q2D_OK;
+    tstart(p, 4);
+    const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
+    if (hipEventRecord(p->ev_fork, p->stream) != hipSuccess ||
+        hipStreamWaitEvent(p->side, p->ev_fork, 0) != hipSuccess)
+        return Q2D_EDEVICE;
+    {
+        SideScope side(p);
+        if ((st = sample_modes(p, P, seed, step)) != Q2D_OK) return st;
+    }
+    if (hipEventRecord(p->ev_modes, p->side) != hipSuccess) return Q2D_EDEVICE;
+    if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
+    if (hipStreamWaitEvent(p->stream, p->ev_modes, 0) != hipSuccess) return Q2D_EDEVICE;
+    st = vjp_passes(p, N, (const int32_t *)p->rb_modes.p, p->rb_coef.p, p_pad, P, p->diag_rb, g,
+                    dq, dpos);
     tstop(p, 4);
     return st;
 }

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epi(int64_t N, int nchunks,
         if (F) {
             F[3 * orig] = (T)(q * o1);
             F[3 * orig + 1] = (T)(q * o2);
-            F[3 * orig + 2] = (T)(q * o3 + (fz0 ? fz0[i] : 0.0));
+            F[3 * orig + 2] = (T)(q * (o3 + (fz0 ? fz0[i] : 0.0)));
         }
         e = q * ph;
     }
@@ -72,6 +72,65 @@ __global__ __launch_bounds__(EPI_THREADS) void k_energy(const double *__restrict
 
 __global__ void k_set_zero(double *E) { E[0] = 0.0; }
 
+// sum of the chunks' outputs for particle i (sorted order), in FP64
+template <typename T>
+__device__ inline void chunk_sum(const T *__restrict__ outk, int64_t N, int nchunks, int64_t i,
+                                 double o[4]) {
+    o[0] = o[1] = o[2] = o[3] = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+        const T *v = outk + ((int64_t)c * N + i) * 4;
+        o[0] += (double)v[0];
+        o[1] += (double)v[1];
+        o[2] += (double)v[2];
+        o[3] += (double)v[3];
+    }
+}
+
+// the field (force per unit target charge) of the current sources, sorted order
+template <typename T>
+__global__ __launch_bounds__(EPI_THREADS) void k_field(int64_t N, int nchunks,
+                                                       const T *__restrict__ outk,
+                                                       const double *__restrict__ fz0,
+                                                       double *__restrict__ fq) {
+    const int64_t i = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
+    if (i >= N) return;
+    double o[4];
+    chunk_sum(outk, N, nchunks, i, o);
+    fq[3 * i] = o[1];
+    fq[3 * i + 1] = o[2];
+    fq[3 * i + 2] = o[3] + fz0[i];
+}
+
+// Adjoint of phi(pos, q) for weights g (Sec. 2.2 pair sum, App. E forces):
+// phi_i = sum_j G(r_i, r_j) q_j with G symmetric, so
+//   dq_j   = sum_i g_i G(r_i, r_j)                    = phi(g)_j
+//   dpos_k = sum_i g_i d phi_i / d r_k = -(g_k f(q)_k + q_k f(g)_k),
+// f(s) being the field of the sources s (the force on a unit charge).
+template <typename T>
+__global__ __launch_bounds__(EPI_THREADS) void k_vjp(int64_t N, int nchunks,
+                                                     const T *__restrict__ outk,
+                                                     const T *__restrict__ qs,
+                                                     const T *__restrict__ gs,
+                                                     const double *__restrict__ phi0,
+                                                     const double *__restrict__ fz0,
+                                                     const double *__restrict__ fq,
+                                                     const int32_t *__restrict__ perm,
+                                                     double diag, double self_c,
+                                                     T *__restrict__ dq, T *__restrict__ dpos) {
+    const int64_t i = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
+    if (i >= N) return;
+    double o[4];
+    chunk_sum(outk, N, nchunks, i, o);
+    const double q = (double)qs[i], g = (double)gs[i];
+    const int64_t orig = perm[i];
+    if (dq) dq[orig] = (T)(o[0] + g * diag + phi0[i] - self_c * g);
+    if (dpos) {
+        dpos[3 * orig] = (T)(-(g * fq[3 * i] + q * o[1]));
+        dpos[3 * orig + 1] = (T)(-(g * fq[3 * i + 1] + q * o[2]));
+        dpos[3 * orig + 2] = (T)(-(g * fq[3 * i + 2] + q * (o[3] + fz0[i])));
+    }
+}
+
 }  // namespace
 
 q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0, void *phi,
@@ -97,6 +156,39 @@ q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0,
             diag, self_c,
             (double *)phi, (double *)F, (double *)p->epart.p);
     if (E) k_energy<<<1, EPI_THREADS, 0, p->stream>>>((const double *)p->epart.p, nb, E);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+q2d_status epilogue_field(Plan *p, int64_t N, int n_chunks) {
+    if (N <= 0) return Q2D_OK;
+    q2d_status st = ensure(p, p->fq, (size_t)N * 3 * sizeof(double));
+    if (st != Q2D_OK) return st;
+    const int nb = (int)((N + EPI_THREADS - 1) / EPI_THREADS);
+    if (p->fp32)
+        k_field<float><<<nb, EPI_THREADS, 0, p->stream>>>(N, n_chunks, (const float *)p->outk.p,
+                                                          (const double *)p->fz0.p,
+                                                          (double *)p->fq.p);
+    else
+        k_field<double><<<nb, EPI_THREADS, 0, p->stream>>>(N, n_chunks, (const double *)p->outk.p,
+                                                           (const double *)p->fz0.p,
+                                                           (double *)p->fq.p);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+q2d_status epilogue_vjp(Plan *p, int64_t N, int n_chunks, double diag, void *dq, void *dpos) {
+    if (N <= 0) return Q2D_OK;
+    const int nb = (int)((N + EPI_THREADS - 1) / EPI_THREADS);
+    const double self_c = 2.0 * p->alpha / sqrt(3.14159265358979323846);
+    if (p->fp32)
+        k_vjp<float><<<nb, EPI_THREADS, 0, p->stream>>>(
+            N, n_chunks, (const float *)p->outk.p, (const float *)p->s_q.p,
+            (const float *)p->s_g.p, (const double *)p->phi0.p, (const double *)p->fz0.p,
+            (const double *)p->fq.p, p->perm, diag, self_c, (float *)dq, (float *)dpos);
+    else
+        k_vjp<double><<<nb, EPI_THREADS, 0, p->stream>>>(
+            N, n_chunks, (const double *)p->outk.p, (const double *)p->s_q.p,
+            (const double *)p->s_g.p, (const double *)p->phi0.p, (const double *)p->fz0.p,
+            (const double *)p->fq.p, p->perm, diag, self_c, (double *)dq, (double *)dpos);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 

@@ -93,6 +93,10 @@ struct Plan {
     Buf keys_a, keys_b, vals_a, vals_b, hist;
     Buf s_ux, s_uy, s_z, s_q;  // sorted SoA
     int32_t *perm = nullptr;   // points into vals_a or vals_b after the sort
+    // sources of the scans: sorted q unless set (the adjoint pass points it at s_g)
+    const void *src = nullptr;
+    Buf s_g;                   // sorted adjoint weights g (T)
+    Buf fq;                    // field of the charges q per particle, sorted order (FP64 x 3)
 
     // k != 0 scans
     Buf spans;                 // FP64 complex W,G per (segment, pair)
@@ -150,6 +154,15 @@ q2d_status k0_run(Plan *p, int64_t N);
 // combine, unsort, energy
 q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0, void *phi,
                     void *F, double *E);
+
+// adjoint: sorted copy of the caller's weights g into s_g
+q2d_status gather_sources(Plan *p, const void *g, int64_t N);
+// adjoint: keep the field of the current sources (charges q) in p->fq
+q2d_status epilogue_field(Plan *p, int64_t N, int n_chunks);
+// adjoint: with the outputs of the pass over sources g, write
+//   dq = phi(g) (j = i constant, k = 0 and self terms included) and
+//   dpos = -(g * field(q) + q * field(g)), unsorted
+q2d_status epilogue_vjp(Plan *p, int64_t N, int n_chunks, double diag, void *dq, void *dpos);
 
 // short range
 q2d_status short_range_run(Plan *p, const void *pos, const void *q, int64_t N, void *phi, void *F,

@@ -5,6 +5,8 @@
 //   K_0'(z) = sum_l (w_l/sqrt(pi)) [2/s_l - (s_l + 2/s_l - 2 alpha z) e^{-beta_l z}]
 //   phi^0_i = -(2 pi/A) sum_j q_j K_0(|z_ij|)   (j = i included: K_0(0))
 //   F^0_z,i = (2 pi/A) q_i sum_{j != i} q_j sgn(z_i - z_j) K_0'(|z_ij|)
+// The kernels take the sources q_j as an array (the charges, or the adjoint
+// weights) and store phi^0 and the field F^0_z,i / q_i.
 // The z e^{-beta z} terms are split as z_ij e^{-beta z_ij} = z_i e^{..} - z_j e^{..}
 // (j below i), so every term is a plain decayed scan of one of two real
 // sources, q_j and q_j z_j; the linear terms are the beta = 0 scans (prefix
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(128) void k0_sweep(const T *__restrict__ zs,
     for (int j = 0; j < S0; ++j) {
         if (j < n) {
             phi0[i0 + j] = -two_pi_over_A * (ph[j] + q[j] * k0_self);
-            fz0[i0 + j] = two_pi_over_A * q[j] * fz[j];
+            fz0[i0 + j] = two_pi_over_A * fz[j];  // field: the target charge is applied later
         }
     }
 }
@@ -206,24 +208,25 @@ q2d_status k0_run(Plan *p, int64_t N) {
     if ((st = ensure(p, p->fz0, (size_t)N * sizeof(double))) != Q2D_OK) return st;
     if ((st = spans_k0(p, nseg, S0, N)) != Q2D_OK) return st;
     const int nb = (nseg + 127) / 128;
+    const void *qsrc = p->src ? p->src : p->s_q.p;
     const double PI = 3.14159265358979323846;
     const double tpa = 2.0 * PI / (p->Lx * p->Ly);
     if (p->fp32)
-        k0_agg<float><<<nb, 128, 0, p->stream>>>((const float *)p->s_z.p, (const float *)p->s_q.p,
+        k0_agg<float><<<nb, 128, 0, p->stream>>>((const float *)p->s_z.p, (const float *)qsrc,
                                                   N, nseg, p->pp, (cx<double> *)p->agg0.p);
     else
         k0_agg<double><<<nb, 128, 0, p->stream>>>((const double *)p->s_z.p,
-                                                   (const double *)p->s_q.p, N, nseg, p->pp,
+                                                   (const double *)qsrc, N, nseg, p->pp,
                                                    (cx<double> *)p->agg0.p);
     if ((st = carry_k0(p, nseg, S0, N)) != Q2D_OK) return st;
     if (p->fp32)
         k0_sweep<float><<<nb, 128, 0, p->stream>>>(
-            (const float *)p->s_z.p, (const float *)p->s_q.p, N, nseg, p->pp, p->c_lin,
+            (const float *)p->s_z.p, (const float *)qsrc, N, nseg, p->pp, p->c_lin,
             p->k0_self, tpa, (const cx<double> *)p->agg0.p, (double *)p->phi0.p,
             (double *)p->fz0.p);
     else
         k0_sweep<double><<<nb, 128, 0, p->stream>>>(
-            (const double *)p->s_z.p, (const double *)p->s_q.p, N, nseg, p->pp, p->c_lin,
+            (const double *)p->s_z.p, (const double *)qsrc, N, nseg, p->pp, p->c_lin,
             p->k0_self, tpa, (const cx<double> *)p->agg0.p, (double *)p->phi0.p,
             (double *)p->fz0.p);
     tstop(p, 3);

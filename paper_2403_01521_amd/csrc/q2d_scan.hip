@@ -845,7 +845,7 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
     ka.ux = (const U *)p->s_ux.p;
     ka.uy = (const U *)p->s_uy.p;
     ka.z = (const T *)p->s_z.p;
-    ka.q = (const T *)p->s_q.p;
+    ka.q = (const T *)(p->src ? p->src : p->s_q.p);
     ka.modes = modes;
     ka.mstride = cstride;
     ka.coef = (const T *)coef;

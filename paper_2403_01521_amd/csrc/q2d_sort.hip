@@ -218,6 +218,14 @@ __global__ __launch_bounds__(256) void k_gather(const T *__restrict__ pos,
     qs[i] = q[o];
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather1(const T *__restrict__ in,
+                                                 const int32_t *__restrict__ perm, int64_t N,
+                                                 T *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) out[i] = in[perm[i]];
+}
+
 template <typename T, typename K>
 q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
     const T *pos = (const T *)pos_v;
@@ -265,6 +273,20 @@ q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
 }
 
 }  // namespace
+
+q2d_status gather_sources(Plan *p, const void *g, int64_t N) {
+    const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+    q2d_status st = ensure(p, p->s_g, N * tsz);
+    if (st != Q2D_OK) return st;
+    const int nb = (int)((N + 255) / 256);
+    if (p->fp32)
+        k_gather1<float><<<nb, 256, 0, p->stream>>>((const float *)g, p->perm, N,
+                                                    (float *)p->s_g.p);
+    else
+        k_gather1<double><<<nb, 256, 0, p->stream>>>((const double *)g, p->perm, N,
+                                                     (double *)p->s_g.p);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
 
 q2d_status sort_and_stage(Plan *p, const void *pos, const void *q, int64_t N) {
     tstart(p, 2);

@@ -66,26 +66,27 @@ def surface_excess_ions(rng, n_pos, n_neg, box, n_excess, layer):
 
 
 def mixed_valence_ions(rng, n, box):
-    """|q| in {1, 2} with random signs, rebalanced to zero net charge."""
+    """|q| in {1, 2} iid, signs half and half, magnitudes rebalanced to zero net
+    charge (n even): while the net charge is positive, a +2 becomes +1 or a -1
+    becomes -2 (and conversely), visiting particles in a random order."""
     Lx, Ly, Lz = box
     pos = np.empty((n, 3))
     pos[:, 0] = rng.uniform(0.0, Lx, n)
     pos[:, 1] = rng.uniform(0.0, Ly, n)
     pos[:, 2] = rng.uniform(0.0, Lz, n)
     mag = rng.integers(1, 3, n).astype(np.float64)
-    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    sign = np.ones(n)
+    sign[rng.permutation(n)[: n // 2]] = -1.0
     q = mag * sign
-    # flip signs of unit charges until neutral (net charge is always even-reachable
-    # by flipping a +-1 or a +-2)
     net = q.sum()
-    i = 0
-    order = rng.permutation(n)
-    while net != 0 and i < n:
-        j = order[i]
-        if np.sign(q[j]) == np.sign(net) and abs(q[j]) <= abs(net) / 2:
-            net -= 2 * q[j]
-            q[j] = -q[j]
-        i += 1
+    for j in rng.permutation(n):
+        if net == 0:
+            break
+        s = np.sign(net)
+        # lower the magnitude of a charge of the net's sign, or raise one of the other
+        if q[j] == 2 * s or q[j] == -s:
+            q[j] -= s
+            net -= s
     if net != 0:
         raise RuntimeError("could not neutralise")
     return pos, q
