@@ -211,6 +211,57 @@ q2d_status q2d_soe_fit(int32_t M, double *w, double *s, double *sup_err);
 q2d_status q2d_plan_timing_enable(q2d_plan_t plan, int32_t mask);
 q2d_status q2d_plan_timing_read(q2d_plan_t plan, int32_t which, double *ms_total, int64_t *count);
 
+/*
+ * Replica batches -- R independent systems advanced by one random-batch step
+ * together (the same alpha, SOE table and P; each replica its own box
+ * Lx_r x Ly_r x [0, Lz_r], particle count n_r, lattice sum H_r and j = i
+ * constant).  Every kernel family runs once for all replicas.
+ *
+ * q2d_batch_create: boxes = host array R x 3 (Lx, Ly, Lz); n = host array R
+ *   (n_r >= 0, sum <= 2^31 - 1).  opts: precision, p_max (>= 1, the largest
+ *   P), thin, validate (n_max is ignored).  Q2D_EINVAL on bad arguments.
+ * q2d_batch_rbm_step: pos (sum n_r x 3) and q (sum n_r): device inputs with
+ *   the replicas concatenated in order; phi, F: device outputs in the same
+ *   layout (or NULL); E: device array of R doubles (or NULL), E_r =
+ *   1/2 sum q_i phi_i over replica r.  Replica r draws its P modes exactly as
+ *   q2d_rbm_step does with seed_r = seed + r * 0x9E3779B97F4A7C15 (mod 2^64)
+ *   and the same step; modes_out: device int32 array R x P x 2, or NULL.
+ *   Each replica's result is the single-system q2d_rbm_step result for its
+ *   box and seed_r (Alg. 2, Fourier part).
+ * q2d_batch_set_segment: segment length S (multiple of 64 in [64, 512]) of
+ *   the replicas' layout; q2d_batch_tune times S = 64, 128, 256, 512 on the
+ *   caller's data (a few steps each; phi, F, E serve as scratch), keeps the
+ *   fastest and returns it in *segment.
+ * q2d_batch_capture: runs one step eagerly (step0), then captures one step
+ *   into a hipGraph on the batch's internal stream; the graph reads its step
+ *   number from device memory (starting at step0) and increments it last, so
+ *   q2d_batch_replay(n) enqueues n steps step0, step0 + 1, ... on the batch's
+ *   stream reading pos, q and writing phi, F, E at the captured addresses
+ *   (keep them alive; update pos in place between replays).  A new layout
+ *   (set_segment, tune) drops the graph (replay then returns Q2D_EUNSUPPORTED).
+ * q2d_batch_info: current S, padded particle count, and host copies of H_r
+ *   and the random-batch j = i constants (arrays of R, or NULL).
+ * q2d_batch_check: as q2d_plan_check.
+ */
+typedef struct q2d_batch *q2d_batch_t;
+q2d_status q2d_batch_create(int32_t R, const double *boxes, const int64_t *n, double alpha,
+                            int32_t M, const double *w, const double *s, const q2d_opts *opts,
+                            void *stream, q2d_batch_t *out);
+q2d_status q2d_batch_destroy(q2d_batch_t batch);
+q2d_status q2d_batch_set_stream(q2d_batch_t batch, void *stream);
+q2d_status q2d_batch_set_segment(q2d_batch_t batch, int32_t S);
+q2d_status q2d_batch_info(q2d_batch_t batch, int32_t *segment, int64_t *n_padded, double *H,
+                          double *diag_rb);
+q2d_status q2d_batch_rbm_step(q2d_batch_t batch, const void *pos, const void *q, int32_t P,
+                              uint64_t seed, uint64_t step, void *phi, void *F, double *E,
+                              int32_t *modes_out);
+q2d_status q2d_batch_tune(q2d_batch_t batch, const void *pos, const void *q, int32_t P,
+                          uint64_t seed, void *phi, void *F, double *E, int32_t *segment);
+q2d_status q2d_batch_capture(q2d_batch_t batch, const void *pos, const void *q, int32_t P,
+                             uint64_t seed, uint64_t step0, void *phi, void *F, double *E);
+q2d_status q2d_batch_replay(q2d_batch_t batch, int32_t n_steps);
+q2d_status q2d_batch_check(q2d_batch_t batch);
+
 /* Static description of a status code. */
 const char *q2d_status_string(q2d_status st);
 

@@ -33,7 +33,10 @@ TIMING_ALL = 31
 
 EXPORTS = ("q2d_plan_create", "q2d_plan_destroy", "q2d_plan_set_stream", "q2d_plan_info",
            "q2d_long_range", "q2d_rbm_step", "q2d_long_range_vjp", "q2d_rbm_step_vjp",
-           "q2d_modes_eval", "q2d_short_range",
+           "q2d_modes_eval", "q2d_short_range", "q2d_batch_create", "q2d_batch_destroy",
+           "q2d_batch_set_stream", "q2d_batch_set_segment", "q2d_batch_info",
+           "q2d_batch_rbm_step", "q2d_batch_tune", "q2d_batch_capture", "q2d_batch_replay",
+           "q2d_batch_check",
            "q2d_plan_check",
            "q2d_soe_fit", "q2d_plan_timing_enable", "q2d_plan_timing_read",
            "q2d_status_string")
@@ -87,6 +90,19 @@ def load_library(path=None):
     lib.q2d_soe_fit.argtypes = [i32, dp, dp, dp]
     lib.q2d_plan_timing_enable.argtypes = [vp, i32]
     lib.q2d_plan_timing_read.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.q2d_batch_create.argtypes = [i32, dp, i64p, dbl, i32, dp, dp, ctypes.POINTER(_Opts), vp,
+                                     ctypes.POINTER(vp)]
+    lib.q2d_batch_destroy.argtypes = [vp]
+    lib.q2d_batch_set_stream.argtypes = [vp, vp]
+    lib.q2d_batch_set_segment.argtypes = [vp, i32]
+    lib.q2d_batch_info.argtypes = [vp, i32p, i64p, dp, dp]
+    lib.q2d_batch_rbm_step.argtypes = [vp, vp, vp, i32, u64, u64, vp, vp, vp, vp]
+    lib.q2d_batch_tune.argtypes = [vp, vp, vp, i32, u64, vp, vp, vp, i32p]
+    lib.q2d_batch_capture.argtypes = [vp, vp, vp, i32, u64, u64, vp, vp, vp]
+    lib.q2d_batch_replay.argtypes = [vp, i32]
+    lib.q2d_batch_check.argtypes = [vp]
     lib.q2d_status_string.argtypes = [ctypes.c_int]
     lib.q2d_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -287,3 +303,136 @@ class Plan:
         _check(self._lib.q2d_plan_timing_read(self._h, int(which), ctypes.byref(ms),
                                               ctypes.byref(cnt)), "timing_read")
         return ms.value, cnt.value
+
+
+REPLICA_SEED_STEP = 0x9E3779B97F4A7C15
+
+
+def replica_seed(seed, r):
+    """Philox key with which replica r of a batch draws its modes."""
+    return (int(seed) + int(r) * REPLICA_SEED_STEP) % (1 << 64)
+
+
+class Batch:
+    """R independent systems advanced together (q2d_batch_create).
+
+    boxes: R x 3 (Lx, Ly, Lz); counts: R particle counts.  Positions and charges
+    are passed concatenated by replica; outputs come back in the same layout,
+    with one energy per replica."""
+
+    def __init__(self, boxes, counts, alpha, w, s, *, precision="fp32", p_max, thin=1,
+                 validate=False, stream=None):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        self.boxes = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
+        self.counts = np.ascontiguousarray(np.asarray(counts, dtype=np.int64))
+        self.R = len(self.counts)
+        if self.boxes.shape[0] != self.R:
+            raise ValueError("one box per replica")
+        self.N = int(self.counts.sum())
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        w = _interleave(w)
+        s = _interleave(s)
+        opts = _Opts(FP32 if precision == "fp32" else FP64, int(thin), max(self.N, 1),
+                     int(p_max), 1 if validate else 0)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        h = ctypes.c_void_p()
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib.q2d_batch_create(self.R, self.boxes.ctypes.data_as(dp),
+                                    self.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    float(alpha), len(w) // 2, w.ctypes.data_as(dp),
+                                    s.ctypes.data_as(dp), ctypes.byref(opts),
+                                    ctypes.c_void_p(stream), ctypes.byref(h)), "q2d_batch_create")
+        self._h = h
+        self._lib = lib
+        self._captured = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.q2d_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def _sync_stream(self):
+        st = self._torch.cuda.current_stream().cuda_stream
+        if st != self._stream:
+            _check(self._lib.q2d_batch_set_stream(self._h, ctypes.c_void_p(st)),
+                   "q2d_batch_set_stream")
+            self._stream = st
+
+    def _io(self, pos, q):
+        t = self._torch
+        if not (pos.is_cuda and q.is_cuda) or pos.dtype != self.dtype or q.dtype != self.dtype:
+            raise ValueError("pos, q must be device tensors of the batch's dtype")
+        pos = pos.contiguous()
+        q = q.contiguous()
+        if pos.shape != (self.N, 3) or q.shape != (self.N,):
+            raise ValueError("pos must be (sum n_r, 3) and q (sum n_r,)")
+        phi = t.empty(self.N, dtype=self.dtype, device=pos.device)
+        F = t.empty((self.N, 3), dtype=self.dtype, device=pos.device)
+        E = t.empty(self.R, dtype=t.float64, device=pos.device)
+        return pos, q, phi, F, E
+
+    def info(self):
+        seg = ctypes.c_int32(0)
+        npad = ctypes.c_int64(0)
+        H = np.zeros(self.R)
+        D = np.zeros(self.R)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(self._lib.q2d_batch_info(self._h, ctypes.byref(seg), ctypes.byref(npad),
+                                        H.ctypes.data_as(dp), D.ctypes.data_as(dp)),
+               "q2d_batch_info")
+        return dict(segment=seg.value, n_padded=npad.value, H=H, diag_rb=D)
+
+    def rbm_step(self, pos, q, P, seed, step):
+        """(phi, F, E[R], modes[R, P, 2]) device tensors."""
+        self._sync_stream()
+        pos, q, phi, F, E = self._io(pos, q)
+        modes = self._torch.empty((self.R, P, 2), dtype=self._torch.int32, device=pos.device)
+        _check(self._lib.q2d_batch_rbm_step(self._h, pos.data_ptr(), q.data_ptr(), int(P),
+                                            ctypes.c_uint64(seed), ctypes.c_uint64(step),
+                                            phi.data_ptr(), F.data_ptr(), E.data_ptr(),
+                                            modes.data_ptr()), "q2d_batch_rbm_step")
+        return phi, F, E, modes
+
+    def set_segment(self, S):
+        _check(self._lib.q2d_batch_set_segment(self._h, int(S)), "q2d_batch_set_segment")
+
+    def tune(self, pos, q, P, seed=0):
+        """Time the segment lengths on these inputs, keep the fastest, return it."""
+        self._sync_stream()
+        pos, q, phi, F, E = self._io(pos, q)
+        seg = ctypes.c_int32(0)
+        _check(self._lib.q2d_batch_tune(self._h, pos.data_ptr(), q.data_ptr(), int(P),
+                                        ctypes.c_uint64(seed), phi.data_ptr(), F.data_ptr(),
+                                        E.data_ptr(), ctypes.byref(seg)), "q2d_batch_tune")
+        return seg.value
+
+    def capture(self, pos, q, P, seed, step0):
+        """Capture one step as a graph; returns the (phi, F, E) tensors every
+        replay writes.  pos and q are read at replay time (update in place)."""
+        self._sync_stream()
+        pos, q, phi, F, E = self._io(pos, q)
+        _check(self._lib.q2d_batch_capture(self._h, pos.data_ptr(), q.data_ptr(), int(P),
+                                           ctypes.c_uint64(seed), ctypes.c_uint64(step0),
+                                           phi.data_ptr(), F.data_ptr(), E.data_ptr()),
+               "q2d_batch_capture")
+        self._captured = (pos, q, phi, F, E)
+        return phi, F, E
+
+    def replay(self, n=1):
+        self._sync_stream()
+        _check(self._lib.q2d_batch_replay(self._h, int(n)), "q2d_batch_replay")
+
+    def check(self):
+        return int(self._lib.q2d_batch_check(self._h))
+

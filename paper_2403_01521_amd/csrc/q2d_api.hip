@@ -97,6 +97,49 @@ double soe_K0_at(double k, double alpha, const std::vector<cd> &w, const std::ve
     return (2.0 * alpha / (std::sqrt(PI) * k) * acc).real();
 }
 
+// Direct lattice sums of a box (Sec. 4.1, eq. hk; the j = i constants of the
+// k != 0 modes): H = sum_{k != 0} e^{-k^2/4a^2}, and D = (pi/A) sum e^{-k^2/4a^2}
+// K_k(0) over the whole lattice (random batch) and over 0 < |k| <= k_c (exact-k).
+// Terms with e^{-k^2/4a^2} < 1e-18 are dropped.
+void lattice_sums(double Lx, double Ly, double alpha, double k_c, const std::vector<cd> &wc,
+                  const std::vector<cd> &sc, double *H, double *diag_rb, double *diag_exact) {
+    const double A = Lx * Ly;
+    const double kmax = 2.0 * alpha * std::sqrt(std::log(1e18));
+    const int mxm = (int)std::ceil(kmax * Lx / (2 * PI)), mym = (int)std::ceil(kmax * Ly / (2 * PI));
+    double gx = 0, gy = 0;
+    for (int m = -mxm; m <= mxm; ++m) gx += std::exp(-std::pow(2 * PI * m / Lx, 2) / (4 * alpha * alpha));
+    for (int m = -mym; m <= mym; ++m) gy += std::exp(-std::pow(2 * PI * m / Ly, 2) / (4 * alpha * alpha));
+    *H = gx * gy - 1.0;
+    double drb = 0.0, dex = 0.0;
+    for (int mx = -mxm; mx <= mxm; ++mx)
+        for (int my = -mym; my <= mym; ++my) {
+            if (mx == 0 && my == 0) continue;
+            const double kx = 2 * PI * mx / Lx, ky = 2 * PI * my / Ly;
+            const double k2 = kx * kx + ky * ky;
+            if (k2 > kmax * kmax) continue;
+            const double k = std::sqrt(k2);
+            const double t = std::exp(-k2 / (4 * alpha * alpha)) * soe_K0_at(k, alpha, wc, sc);
+            drb += t;
+            if (k_c > 0 && k2 <= k_c * k_c) dex += t;
+        }
+    *diag_rb = PI / A * drb;
+    *diag_exact = 0.0;
+    if (k_c > 0) {
+        // exact-k terms beyond kmax (if k_c > kmax) are below 1e-18 of the first
+        const int ex = (int)std::floor(k_c * Lx / (2 * PI)), ey = (int)std::floor(k_c * Ly / (2 * PI));
+        if (k_c > kmax)
+            for (int mx = -ex; mx <= ex; ++mx)
+                for (int my = -ey; my <= ey; ++my) {
+                    const double kx = 2 * PI * mx / Lx, ky = 2 * PI * my / Ly;
+                    const double k2 = kx * kx + ky * ky;
+                    if ((mx == 0 && my == 0) || k2 <= kmax * kmax || k2 > k_c * k_c) continue;
+                    const double k = std::sqrt(k2);
+                    dex += std::exp(-k2 / (4 * alpha * alpha)) * soe_K0_at(k, alpha, wc, sc);
+                }
+        *diag_exact = PI / A * dex;
+    }
+}
+
 struct Fit {
     std::vector<cd> w, s;
 };
@@ -176,29 +219,6 @@ __global__ void k_modes_out(const int32_t *modes, int P, int p_pad, int32_t *out
     }
 }
 
-// Enqueue on the side stream within a scope: the launchers use p->stream.
-struct SideScope {
-    Plan *p;
-    hipStream_t saved;
-    explicit SideScope(Plan *p_) : p(p_), saved(p_->stream) { p->stream = p->side; }
-    ~SideScope() { p->stream = saved; }
-};
-
-// The k = 0 term on the side stream once the sorted data exist; the main
-// stream must wait for ev_k0 before the epilogue reads phi0 / fz0.
-q2d_status k0_side(Plan *p, int64_t N) {
-    if (hipEventRecord(p->ev_sorted, p->stream) != hipSuccess ||
-        hipStreamWaitEvent(p->side, p->ev_sorted, 0) != hipSuccess)
-        return Q2D_EDEVICE;
-    q2d_status st;
-    {
-        SideScope side(p);
-        st = k0_run(p, N);
-    }
-    if (st != Q2D_OK) return st;
-    return hipEventRecord(p->ev_k0, p->side) == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
-}
-
 // The two passes of the adjoint once the particles are sorted (and, for the
 // random batch, the modes drawn): sources q keep their field in p->fq, then
 // sources g give phi(g) and f(g), combined by the adjoint epilogue.
@@ -224,6 +244,229 @@ q2d_status vjp_passes(Plan *p, int64_t N, const int32_t *modes, const void *coef
 }
 
 }  // namespace
+
+namespace q2d {
+
+q2d_status k0_side(Plan *p, int64_t N) {
+    if (hipEventRecord(p->ev_sorted, p->stream) != hipSuccess ||
+        hipStreamWaitEvent(p->side, p->ev_sorted, 0) != hipSuccess)
+        return Q2D_EDEVICE;
+    q2d_status st;
+    {
+        SideScope side(p);
+        st = k0_run(p, N);
+    }
+    if (st != Q2D_OK) return st;
+    return hipEventRecord(p->ev_k0, p->side) == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+// Validation and host set-up of a plan (allocated by the caller); on failure
+// the caller releases it with plan_release.
+q2d_status plan_init(Plan *p, double Lx, double Ly, double Lz, double alpha, double r_c,
+                     double k_c, int32_t M, const double *w, const double *s, const q2d_opts *opts,
+                     void *stream) {
+    if (!opts || !w || !s) return Q2D_EINVAL;
+    if (!(Lx > 0 && Ly > 0 && Lz > 0 && alpha > 0) || !std::isfinite(Lx) || !std::isfinite(Ly) ||
+        !std::isfinite(Lz) || !std::isfinite(alpha) || std::isnan(r_c) || std::isnan(k_c))
+        return Q2D_EINVAL;
+    if (M < 2 || M > 2 * MAX_PAIRS || (M % 2)) return Q2D_EINVAL;
+    if (opts->precision != Q2D_FP64 && opts->precision != Q2D_FP32) return Q2D_EINVAL;
+    if (opts->n_max <= 0 || opts->n_max > ((int64_t)1 << 31) - 1 || opts->p_max < 0 ||
+        opts->thin < 0)
+        return Q2D_EINVAL;
+    if (r_c > 0 && r_c > 0.5 * std::min(Lx, Ly)) return Q2D_EINVAL;
+    // SOE table: conjugate-closed, Re s > 0, no real node
+    std::vector<cd> wc(M), sc(M);
+    for (int l = 0; l < M; ++l) {
+        wc[l] = cd(w[2 * l], w[2 * l + 1]);
+        sc[l] = cd(s[2 * l], s[2 * l + 1]);
+        if (!std::isfinite(wc[l].real()) || !std::isfinite(wc[l].imag()) ||
+            !std::isfinite(sc[l].real()) || !std::isfinite(sc[l].imag()))
+            return Q2D_EINVAL;
+        if (!(sc[l].real() > 0) || std::fabs(sc[l].imag()) <= 1e-12 * std::abs(sc[l]))
+            return Q2D_EINVAL;
+    }
+    std::vector<int> partner(M, -1);
+    for (int l = 0; l < M; ++l) {
+        for (int j = 0; j < M; ++j) {
+            if (j == l) continue;
+            if (std::abs(sc[j] - std::conj(sc[l])) <= 1e-10 * std::abs(sc[l]) &&
+                std::abs(wc[j] - std::conj(wc[l])) <= 1e-10 * std::abs(wc[l]) + 1e-300) {
+                partner[l] = j;
+                break;
+            }
+        }
+        if (partner[l] < 0) return Q2D_EINVAL;
+    }
+
+    p->Lx = Lx;
+    p->Ly = Ly;
+    p->Lz = Lz;
+    p->alpha = alpha;
+    p->rc = r_c;
+    p->kc = k_c;
+    p->M = M;
+    p->mh = M / 2;
+    p->opts = *opts;
+    if (p->opts.thin <= 0) p->opts.thin = 1;
+    p->fp32 = opts->precision == Q2D_FP32;
+    p->stream = (hipStream_t)stream;
+    if (hipGetDevice(&p->device) != hipSuccess) return Q2D_EDEVICE;
+    if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_sorted, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_modes, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_k0, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return Q2D_EDEVICE;
+    }
+
+    // pair representatives (Im s > 0) and k = 0 combine coefficients
+    PairParams &pp = p->pp;
+    pp.mh = p->mh;
+    pp.m_all = M;
+    int r = 0;
+    const double sqpi = std::sqrt(PI);
+    for (int l = 0; l < M; ++l) {
+        pp.w_re[l] = wc[l].real();
+        pp.w_im[l] = wc[l].imag();
+        pp.b_re[l] = alpha * sc[l].real();
+        pp.b_im[l] = alpha * sc[l].imag();
+        pp.rep_of[l] = -1;
+        if (sc[l].imag() > 0) {
+            if (r >= MAX_PAIRS) return Q2D_EINVAL;
+            pp.rep_of[l] = r;
+            pp.beta_re[r] = alpha * sc[l].real();
+            pp.beta_im[r] = alpha * sc[l].imag();
+            const cd ws = wc[l] / sqpi;
+            const cd cu = 2.0 * ws / alpha;
+            const cd cv = -2.0 * ws * (2.0 / sc[l]);
+            const cd fu = -2.0 * ws * (sc[l] + 2.0 / sc[l]);
+            const cd fv = 2.0 * ws * (2.0 * alpha);
+            pp.c0u_re[r] = cu.real();
+            pp.c0u_im[r] = cu.imag();
+            pp.c0v_re[r] = cv.real();
+            pp.c0v_im[r] = cv.imag();
+            pp.f0u_re[r] = fu.real();
+            pp.f0u_im[r] = fu.imag();
+            pp.f0v_re[r] = fv.real();
+            pp.f0v_im[r] = fv.imag();
+            ++r;
+        }
+    }
+    if (r != p->mh) return Q2D_EINVAL;
+    cd clin = 0.0, k0s = 0.0;
+    for (int l = 0; l < M; ++l) {
+        clin += wc[l] / sc[l];
+        k0s += wc[l] / (alpha * sqpi);
+    }
+    p->c_lin = 2.0 / sqpi * clin.real();
+    p->k0_self = k0s.real();
+
+    // lattice sums: H and the j = i constants
+    lattice_sums(Lx, Ly, alpha, k_c, wc, sc, &p->H, &p->diag_rb, &p->diag_exact);
+    p->soe_w.assign(w, w + 2 * M);
+    p->soe_s.assign(s, s + 2 * M);
+    const double A = Lx * Ly;
+    q2d_status st = ensure(p, p->status, 64);
+    if (st != Q2D_OK) return st;
+    k_zero_status<<<1, 1, 0, p->stream>>>((int *)p->status.p, (double *)((char *)p->status.p + 16));
+
+    // exact-k half-lattice mode table
+    if (k_c > 0) {
+        std::vector<int32_t> mxv, myv;
+        std::vector<double> wt;
+        const int ex = (int)std::floor(k_c * Lx / (2 * PI)), ey = (int)std::floor(k_c * Ly / (2 * PI));
+        for (int mx = 0; mx <= ex; ++mx)
+            for (int my = (mx == 0 ? 1 : -ey); my <= ey; ++my) {
+                const double kx = 2 * PI * mx / Lx, ky = 2 * PI * my / Ly;
+                const double k2 = kx * kx + ky * ky;
+                if (k2 > k_c * k_c) continue;
+                mxv.push_back(mx);
+                myv.push_back(my);
+                wt.push_back(2.0 * PI / A * std::exp(-k2 / (4 * alpha * alpha)));
+            }
+        p->n_exact = (int64_t)mxv.size();
+        p->n_exact_pad = ((p->n_exact + WAVE - 1) / WAVE) * WAVE;
+        if (p->n_exact > 0) {
+            const int64_t np = p->n_exact_pad;
+            std::vector<int32_t> m2(2 * np, 0);
+            std::vector<double> w2(np, 0.0);
+            for (int64_t i = 0; i < p->n_exact; ++i) {
+                m2[i] = mxv[i];
+                m2[np + i] = myv[i];
+                w2[i] = wt[i];
+            }
+            Buf wbuf;
+            const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+            if ((st = ensure(p, p->exact_modes, m2.size() * sizeof(int32_t))) != Q2D_OK ||
+                (st = ensure(p, p->exact_coef, (size_t)coef_fields(p->mh) * np * tsz)) != Q2D_OK ||
+                (st = ensure(p, wbuf, w2.size() * sizeof(double))) != Q2D_OK) {
+                free_buf(wbuf);
+                return st;
+            }
+            if (hipMemcpyAsync(p->exact_modes.p, m2.data(), m2.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+                hipMemcpyAsync(wbuf.p, w2.data(), w2.size() * sizeof(double),
+                               hipMemcpyHostToDevice, p->stream) != hipSuccess) {
+                free_buf(wbuf);
+                return Q2D_EDEVICE;
+            }
+            st = build_mode_coefs(p, (const int32_t *)p->exact_modes.p, p->n_exact, np,
+                                  (const double *)wbuf.p, 0.0, p->exact_coef.p);
+            (void)hipStreamSynchronize(p->stream);
+            free_buf(wbuf);
+            if (st != Q2D_OK) return st;
+        }
+    }
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return Q2D_EDEVICE;
+    return Q2D_OK;
+}
+
+
+// Wait for the plan's work and free everything it owns (not the struct).
+void box_constants(const Plan *p, double Lx, double Ly, double *H, double *diag_rb) {
+    const int M = p->M;
+    std::vector<cd> wc(M), sc(M);
+    for (int l = 0; l < M; ++l) {
+        wc[l] = cd(p->soe_w[2 * l], p->soe_w[2 * l + 1]);
+        sc[l] = cd(p->soe_s[2 * l], p->soe_s[2 * l + 1]);
+    }
+    double dex = 0.0;
+    lattice_sums(Lx, Ly, p->alpha, 0.0, wc, sc, H, diag_rb, &dex);
+}
+
+void plan_release(Plan *p) {
+    (void)hipSetDevice(p->device);
+    (void)hipStreamSynchronize(p->stream);
+    if (p->side) (void)hipStreamSynchronize(p->side);
+    for (int w = 0; w < 5; ++w) {
+        for (auto e : p->pend_ev[w]) (void)hipEventDestroy(e);
+        p->pend_ev[w].clear();
+    }
+    Buf *bufs[] = {&p->exact_modes, &p->exact_coef, &p->rb_modes, &p->rb_coef, &p->rb_work,
+                   &p->user_modes, &p->user_w, &p->user_coef, &p->s_g, &p->fq,
+                   &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
+                   &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->carry_tmp, &p->outk, &p->spans0,
+                   &p->agg0, &p->carry_tmp0, &p->phi0, &p->fz0, &p->epart, &p->status,
+                   &p->cell_start, &p->cell_count, &p->cell_idx, &p->cell_tmp, &p->rep_box,
+                   &p->rep_H, &p->rep_diag, &p->rep_tpa, &p->rep_of, &p->rep_off, &p->rep_poff,
+                   &p->seg_rep, &p->pperm, &p->epart_rep, &p->step_ctr};
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    for (Buf *b : bufs) free_buf(*b);
+    for (hipEvent_t e : {p->ev_fork, p->ev_sorted, p->ev_modes, p->ev_k0})
+        if (e) (void)hipEventDestroy(e);
+    if (p->side) (void)hipStreamDestroy(p->side);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    p->side = nullptr;
+    p->cap_stream = nullptr;
+}
+
+
+}  // namespace q2d
 
 extern "C" {
 
@@ -270,216 +513,13 @@ q2d_status q2d_plan_create(double Lx, double Ly, double Lz, double alpha, double
                            void *stream, q2d_plan_t *out) {
     if (!out) return Q2D_EINVAL;
     *out = nullptr;
-    if (!opts || !w || !s) return Q2D_EINVAL;
-    if (!(Lx > 0 && Ly > 0 && Lz > 0 && alpha > 0) || !std::isfinite(Lx) || !std::isfinite(Ly) ||
-        !std::isfinite(Lz) || !std::isfinite(alpha) || std::isnan(r_c) || std::isnan(k_c))
-        return Q2D_EINVAL;
-    if (M < 2 || M > 2 * MAX_PAIRS || (M % 2)) return Q2D_EINVAL;
-    if (opts->precision != Q2D_FP64 && opts->precision != Q2D_FP32) return Q2D_EINVAL;
-    if (opts->n_max <= 0 || opts->n_max > ((int64_t)1 << 31) - 1 || opts->p_max < 0 ||
-        opts->thin < 0)
-        return Q2D_EINVAL;
-    if (r_c > 0 && r_c > 0.5 * std::min(Lx, Ly)) return Q2D_EINVAL;
-    // SOE table: conjugate-closed, Re s > 0, no real node
-    std::vector<cd> wc(M), sc(M);
-    for (int l = 0; l < M; ++l) {
-        wc[l] = cd(w[2 * l], w[2 * l + 1]);
-        sc[l] = cd(s[2 * l], s[2 * l + 1]);
-        if (!std::isfinite(wc[l].real()) || !std::isfinite(wc[l].imag()) ||
-            !std::isfinite(sc[l].real()) || !std::isfinite(sc[l].imag()))
-            return Q2D_EINVAL;
-        if (!(sc[l].real() > 0) || std::fabs(sc[l].imag()) <= 1e-12 * std::abs(sc[l]))
-            return Q2D_EINVAL;
-    }
-    std::vector<int> partner(M, -1);
-    for (int l = 0; l < M; ++l) {
-        for (int j = 0; j < M; ++j) {
-            if (j == l) continue;
-            if (std::abs(sc[j] - std::conj(sc[l])) <= 1e-10 * std::abs(sc[l]) &&
-                std::abs(wc[j] - std::conj(wc[l])) <= 1e-10 * std::abs(wc[l]) + 1e-300) {
-                partner[l] = j;
-                break;
-            }
-        }
-        if (partner[l] < 0) return Q2D_EINVAL;
-    }
-
     q2d_plan *p = new (std::nothrow) q2d_plan();
     if (!p) return Q2D_ENOMEM;
-    p->Lx = Lx;
-    p->Ly = Ly;
-    p->Lz = Lz;
-    p->alpha = alpha;
-    p->rc = r_c;
-    p->kc = k_c;
-    p->M = M;
-    p->mh = M / 2;
-    p->opts = *opts;
-    if (p->opts.thin <= 0) p->opts.thin = 1;
-    p->fp32 = opts->precision == Q2D_FP32;
-    p->stream = (hipStream_t)stream;
-    if (hipGetDevice(&p->device) != hipSuccess) {
-        delete p;
-        return Q2D_EDEVICE;
-    }
-    if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_sorted, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_modes, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_k0, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGetLastError();
-        q2d_plan_destroy(p);
-        return Q2D_EDEVICE;
-    }
-
-    // pair representatives (Im s > 0) and k = 0 combine coefficients
-    PairParams &pp = p->pp;
-    pp.mh = p->mh;
-    pp.m_all = M;
-    int r = 0;
-    const double sqpi = std::sqrt(PI);
-    for (int l = 0; l < M; ++l) {
-        pp.w_re[l] = wc[l].real();
-        pp.w_im[l] = wc[l].imag();
-        pp.b_re[l] = alpha * sc[l].real();
-        pp.b_im[l] = alpha * sc[l].imag();
-        pp.rep_of[l] = -1;
-        if (sc[l].imag() > 0) {
-            if (r >= MAX_PAIRS) {
-                delete p;
-                return Q2D_EINVAL;
-            }
-            pp.rep_of[l] = r;
-            pp.beta_re[r] = alpha * sc[l].real();
-            pp.beta_im[r] = alpha * sc[l].imag();
-            const cd ws = wc[l] / sqpi;
-            const cd cu = 2.0 * ws / alpha;
-            const cd cv = -2.0 * ws * (2.0 / sc[l]);
-            const cd fu = -2.0 * ws * (sc[l] + 2.0 / sc[l]);
-            const cd fv = 2.0 * ws * (2.0 * alpha);
-            pp.c0u_re[r] = cu.real();
-            pp.c0u_im[r] = cu.imag();
-            pp.c0v_re[r] = cv.real();
-            pp.c0v_im[r] = cv.imag();
-            pp.f0u_re[r] = fu.real();
-            pp.f0u_im[r] = fu.imag();
-            pp.f0v_re[r] = fv.real();
-            pp.f0v_im[r] = fv.imag();
-            ++r;
-        }
-    }
-    if (r != p->mh) {
-        delete p;
-        return Q2D_EINVAL;
-    }
-    cd clin = 0.0, k0s = 0.0;
-    for (int l = 0; l < M; ++l) {
-        clin += wc[l] / sc[l];
-        k0s += wc[l] / (alpha * sqpi);
-    }
-    p->c_lin = 2.0 / sqpi * clin.real();
-    p->k0_self = k0s.real();
-
-    // lattice sums: H and the j = i constants
-    const double A = Lx * Ly;
-    const double kmax = 2.0 * alpha * std::sqrt(std::log(1e18));
-    {
-        const int mxm = (int)std::ceil(kmax * Lx / (2 * PI)), mym = (int)std::ceil(kmax * Ly / (2 * PI));
-        double gx = 0, gy = 0;
-        for (int m = -mxm; m <= mxm; ++m) gx += std::exp(-std::pow(2 * PI * m / Lx, 2) / (4 * alpha * alpha));
-        for (int m = -mym; m <= mym; ++m) gy += std::exp(-std::pow(2 * PI * m / Ly, 2) / (4 * alpha * alpha));
-        p->H = gx * gy - 1.0;
-        double drb = 0.0, dex = 0.0;
-        for (int mx = -mxm; mx <= mxm; ++mx)
-            for (int my = -mym; my <= mym; ++my) {
-                if (mx == 0 && my == 0) continue;
-                const double kx = 2 * PI * mx / Lx, ky = 2 * PI * my / Ly;
-                const double k2 = kx * kx + ky * ky;
-                if (k2 > kmax * kmax) continue;
-                const double k = std::sqrt(k2);
-                const double t = std::exp(-k2 / (4 * alpha * alpha)) * soe_K0_at(k, alpha, wc, sc);
-                drb += t;
-                if (k_c > 0 && k2 <= k_c * k_c) dex += t;
-            }
-        p->diag_rb = PI / A * drb;
-        if (k_c > 0) {
-            // exact-k terms beyond kmax (if k_c > kmax) are below 1e-18 of the first
-            const int ex = (int)std::floor(k_c * Lx / (2 * PI)), ey = (int)std::floor(k_c * Ly / (2 * PI));
-            if (k_c > kmax)
-                for (int mx = -ex; mx <= ex; ++mx)
-                    for (int my = -ey; my <= ey; ++my) {
-                        const double kx = 2 * PI * mx / Lx, ky = 2 * PI * my / Ly;
-                        const double k2 = kx * kx + ky * ky;
-                        if ((mx == 0 && my == 0) || k2 <= kmax * kmax || k2 > k_c * k_c) continue;
-                        const double k = std::sqrt(k2);
-                        dex += std::exp(-k2 / (4 * alpha * alpha)) * soe_K0_at(k, alpha, wc, sc);
-                    }
-            p->diag_exact = PI / A * dex;
-        }
-    }
-
-    q2d_status st = ensure(p, p->status, 64);
+    const q2d_status st = plan_init(p, Lx, Ly, Lz, alpha, r_c, k_c, M, w, s, opts, stream);
     if (st != Q2D_OK) {
-        q2d_plan_destroy(p);
+        plan_release(p);
+        delete p;
         return st;
-    }
-    k_zero_status<<<1, 1, 0, p->stream>>>((int *)p->status.p, (double *)((char *)p->status.p + 16));
-
-    // exact-k half-lattice mode table
-    if (k_c > 0) {
-        std::vector<int32_t> mxv, myv;
-        std::vector<double> wt;
-        const int ex = (int)std::floor(k_c * Lx / (2 * PI)), ey = (int)std::floor(k_c * Ly / (2 * PI));
-        for (int mx = 0; mx <= ex; ++mx)
-            for (int my = (mx == 0 ? 1 : -ey); my <= ey; ++my) {
-                const double kx = 2 * PI * mx / Lx, ky = 2 * PI * my / Ly;
-                const double k2 = kx * kx + ky * ky;
-                if (k2 > k_c * k_c) continue;
-                mxv.push_back(mx);
-                myv.push_back(my);
-                wt.push_back(2.0 * PI / A * std::exp(-k2 / (4 * alpha * alpha)));
-            }
-        p->n_exact = (int64_t)mxv.size();
-        p->n_exact_pad = ((p->n_exact + WAVE - 1) / WAVE) * WAVE;
-        if (p->n_exact > 0) {
-            const int64_t np = p->n_exact_pad;
-            std::vector<int32_t> m2(2 * np, 0);
-            std::vector<double> w2(np, 0.0);
-            for (int64_t i = 0; i < p->n_exact; ++i) {
-                m2[i] = mxv[i];
-                m2[np + i] = myv[i];
-                w2[i] = wt[i];
-            }
-            Buf wbuf;
-            const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
-            if ((st = ensure(p, p->exact_modes, m2.size() * sizeof(int32_t))) != Q2D_OK ||
-                (st = ensure(p, p->exact_coef, (size_t)coef_fields(p->mh) * np * tsz)) != Q2D_OK ||
-                (st = ensure(p, wbuf, w2.size() * sizeof(double))) != Q2D_OK) {
-                free_buf(wbuf);
-                q2d_plan_destroy(p);
-                return st;
-            }
-            if (hipMemcpyAsync(p->exact_modes.p, m2.data(), m2.size() * sizeof(int32_t),
-                               hipMemcpyHostToDevice, p->stream) != hipSuccess ||
-                hipMemcpyAsync(wbuf.p, w2.data(), w2.size() * sizeof(double),
-                               hipMemcpyHostToDevice, p->stream) != hipSuccess) {
-                free_buf(wbuf);
-                q2d_plan_destroy(p);
-                return Q2D_EDEVICE;
-            }
-            st = build_mode_coefs(p, (const int32_t *)p->exact_modes.p, p->n_exact, np,
-                                  (const double *)wbuf.p, 0.0, p->exact_coef.p);
-            (void)hipStreamSynchronize(p->stream);
-            free_buf(wbuf);
-            if (st != Q2D_OK) {
-                q2d_plan_destroy(p);
-                return st;
-            }
-        }
-    }
-    if (hipStreamSynchronize(p->stream) != hipSuccess) {
-        q2d_plan_destroy(p);
-        return Q2D_EDEVICE;
     }
     *out = p;
     return Q2D_OK;
@@ -487,23 +527,7 @@ q2d_status q2d_plan_create(double Lx, double Ly, double Lz, double alpha, double
 
 q2d_status q2d_plan_destroy(q2d_plan_t p) {
     if (!p) return Q2D_EINVAL;
-    (void)hipSetDevice(p->device);
-    (void)hipStreamSynchronize(p->stream);
-    if (p->side) (void)hipStreamSynchronize(p->side);
-    for (int w = 0; w < 5; ++w) {
-        for (auto e : p->pend_ev[w]) (void)hipEventDestroy(e);
-        p->pend_ev[w].clear();
-    }
-    Buf *bufs[] = {&p->exact_modes, &p->exact_coef, &p->rb_modes, &p->rb_coef, &p->rb_work,
-                   &p->user_modes, &p->user_w, &p->user_coef, &p->s_g, &p->fq,
-                   &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
-                   &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->carry_tmp, &p->outk, &p->spans0,
-                   &p->agg0, &p->carry_tmp0, &p->phi0, &p->fz0, &p->epart, &p->status,
-                   &p->cell_start, &p->cell_count, &p->cell_idx, &p->cell_tmp};
-    for (Buf *b : bufs) free_buf(*b);
-    for (hipEvent_t e : {p->ev_fork, p->ev_sorted, p->ev_modes, p->ev_k0})
-        if (e) (void)hipEventDestroy(e);
-    if (p->side) (void)hipStreamDestroy(p->side);
+    plan_release(p);
     delete p;
     return Q2D_OK;
 }
@@ -681,6 +705,14 @@ q2d_status q2d_short_range(q2d_plan_t p, const void *pos, const void *q, int64_t
 
 q2d_status q2d_plan_check(q2d_plan_t p) {
     if (!p) return Q2D_EINVAL;
+    return plan_check(p);
+}
+
+}  // extern "C"
+
+namespace q2d {
+
+q2d_status plan_check(Plan *p) {
     if (hipSetDevice(p->device) != hipSuccess) return Q2D_EDEVICE;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return Q2D_EDEVICE;
     int bits = 0;
@@ -690,6 +722,10 @@ q2d_status q2d_plan_check(q2d_plan_t p) {
     if (hipStreamSynchronize(p->stream) != hipSuccess) return Q2D_EDEVICE;
     return (q2d_status)first_error(bits);
 }
+
+}  // namespace q2d
+
+extern "C" {
 
 q2d_status q2d_plan_timing_enable(q2d_plan_t p, int32_t mask) {
     if (!p) return Q2D_EINVAL;

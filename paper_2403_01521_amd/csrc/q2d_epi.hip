@@ -7,6 +7,8 @@
 // D is the configuration-independent j = i constant of the k != 0 modes.
 // The energy is reduced in a fixed order (block tree, then one block over the
 // block partials), so repeated calls give identical bits.
+#include <algorithm>
+
 #include "q2d_internal.h"
 
 namespace q2d {
@@ -189,6 +191,101 @@ q2d_status epilogue_vjp(Plan *p, int64_t N, int n_chunks, double diag, void *dq,
             N, n_chunks, (const double *)p->outk.p, (const double *)p->s_q.p,
             (const double *)p->s_g.p, (const double *)p->phi0.p, (const double *)p->fz0.p,
             (const double *)p->fq.p, p->perm, diag, self_c, (double *)dq, (double *)dpos);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+namespace {
+
+constexpr int EPB = 64;  // threads per segment in the batch epilogue
+
+// Replica batches: one work-group per segment (a segment lies in one
+// replica), padding skipped, the replica's j = i constant; the energy partial
+// of each segment is reduced in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(EPB) void k_epi_batch(int S, int64_t Npad, int nchunks,
+                                                   const T *__restrict__ outk,
+                                                   const T *__restrict__ qs,
+                                                   const double *__restrict__ phi0,
+                                                   const double *__restrict__ fz0,
+                                                   const int32_t *__restrict__ pperm,
+                                                   const int32_t *__restrict__ seg_rep,
+                                                   const double *__restrict__ rep_diag,
+                                                   double self_c, T *__restrict__ phi,
+                                                   T *__restrict__ F,
+                                                   double *__restrict__ epart) {
+    __shared__ double red[EPB];
+    const int seg = blockIdx.x;
+    const double diag = rep_diag[seg_rep[seg]];
+    double e = 0.0;
+    for (int t = threadIdx.x; t < S; t += EPB) {
+        const int64_t i = (int64_t)seg * S + t;
+        const int32_t orig = pperm[i];
+        if (orig < 0) continue;
+        double o[4];
+        chunk_sum(outk, Npad, nchunks, i, o);
+        const double q = (double)qs[i];
+        const double ph = o[0] + q * diag + phi0[i] - self_c * q;
+        if (phi) phi[orig] = (T)ph;
+        if (F) {
+            F[3 * (int64_t)orig] = (T)(q * o[1]);
+            F[3 * (int64_t)orig + 1] = (T)(q * o[2]);
+            F[3 * (int64_t)orig + 2] = (T)(q * (o[3] + fz0[i]));
+        }
+        e += q * ph;
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int h = EPB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) epart[seg] = red[0];
+}
+
+// E_r = 1/2 sum of replica r's segment partials, in segment order
+__global__ __launch_bounds__(EPB) void k_energy_batch(const double *__restrict__ epart, int S,
+                                                      const int64_t *__restrict__ poff, int R,
+                                                      double *__restrict__ E) {
+    __shared__ double red[EPB];
+    const int r = blockIdx.x;
+    const int64_t s0 = poff[r] / S, s1 = poff[r + 1] / S;
+    double v = 0.0;
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += EPB) v += epart[s];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = EPB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) E[r] = 0.5 * red[0];
+}
+
+}  // namespace
+
+q2d_status epilogue_batch(Plan *p, int n_chunks, void *phi, void *F, double *E) {
+    const int64_t Npad = p->Npad;
+    const int S = p->S_batch;
+    const int nseg = (int)(Npad / S);
+    q2d_status st = ensure(p, p->epart_rep, (size_t)std::max(nseg, 1) * sizeof(double));
+    if (st != Q2D_OK) return st;
+    const double self_c = 2.0 * p->alpha / sqrt(3.14159265358979323846);
+    if (nseg > 0) {
+        if (p->fp32)
+            k_epi_batch<float><<<nseg, EPB, 0, p->stream>>>(
+                S, Npad, n_chunks, (const float *)p->outk.p, (const float *)p->s_q.p,
+                (const double *)p->phi0.p, (const double *)p->fz0.p, (const int32_t *)p->pperm.p,
+                (const int32_t *)p->seg_rep.p, (const double *)p->rep_diag.p, self_c, (float *)phi,
+                (float *)F, (double *)p->epart_rep.p);
+        else
+            k_epi_batch<double><<<nseg, EPB, 0, p->stream>>>(
+                S, Npad, n_chunks, (const double *)p->outk.p, (const double *)p->s_q.p,
+                (const double *)p->phi0.p, (const double *)p->fz0.p, (const int32_t *)p->pperm.p,
+                (const int32_t *)p->seg_rep.p, (const double *)p->rep_diag.p, self_c,
+                (double *)phi, (double *)F, (double *)p->epart_rep.p);
+    }
+    if (E)
+        k_energy_batch<<<p->R, EPB, 0, p->stream>>>((const double *)p->epart_rep.p, S,
+                                                   (const int64_t *)p->rep_poff.p, p->R, E);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 

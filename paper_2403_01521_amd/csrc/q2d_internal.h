@@ -73,6 +73,7 @@ struct Plan {
     bool fp32 = false;
     PairParams pp{};
     double H = 0, diag_exact = 0, diag_rb = 0, k0_self = 0, c_lin = 0;
+    std::vector<double> soe_w, soe_s;  // the SOE table (2M re, im each)
 
     // exact-k half-lattice mode list (device) and its coefficient table
     int64_t n_exact = 0, n_exact_pad = 0;
@@ -115,6 +116,32 @@ struct Plan {
     // short range
     Buf cell_start, cell_count, cell_idx, cell_tmp;
 
+    // replica batch (R > 0): R independent systems of fixed sizes in one plan.
+    // Inputs are concatenated by replica; after the sort each replica occupies
+    // a run of whole segments of S_batch particles (padding: zero charge at
+    // the replica's top height).
+    int R = 0;
+    int S_batch = 512;
+    int64_t Ntot = 0, Npad = 0;
+    std::vector<double> h_box, h_H, h_diag;      // [R][3], [R], [R]
+    std::vector<int64_t> h_n, h_off, h_poff;     // [R], [R+1], [R+1]
+    Buf rep_box;      // double [R][3]
+    Buf rep_H;        // double [R]
+    Buf rep_diag;     // double [R]: random-batch j = i constant
+    Buf rep_tpa;      // double [R]: 2 pi / A
+    Buf rep_of;       // int32 [Ntot]: replica of each input particle
+    Buf rep_off;      // int64 [R+1]: input offsets
+    Buf rep_poff;     // int64 [R+1]: padded offsets
+    Buf seg_rep;      // int32 [Npad / S_batch]
+    Buf pperm;        // int32 [Npad]: input index of each padded position, -1 for padding
+    Buf epart_rep;    // double [Npad / S_batch]: per-segment energy partials
+    int64_t rep_mstride = 0, rep_cstride = 0;    // per-replica table strides at this P
+    // captured step (hipGraph) reading its step number from step_ctr
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    Buf step_ctr;     // uint64 [1]
+
     // timing
     int timing = 0;  // bit mask of timed kernel families
     hipEvent_t ev[5][2]{};
@@ -126,6 +153,16 @@ struct Plan {
 // growth helper: ensure buffer holds at least `bytes`
 q2d_status ensure(Plan *p, Buf &b, size_t bytes);
 
+// plan set-up shared by single systems and replica batches (q2d_api.hip)
+q2d_status plan_init(Plan *p, double Lx, double Ly, double Lz, double alpha, double r_c,
+                     double k_c, int32_t M, const double *w, const double *s, const q2d_opts *opts,
+                     void *stream);
+void plan_release(Plan *p);
+// wait for the stream, read and clear the device status word
+q2d_status plan_check(Plan *p);
+// H and the random-batch j = i constant of a box for the plan's SOE table
+void box_constants(const Plan *p, double Lx, double Ly, double *H, double *diag_rb);
+
 // timing helpers
 void tstart(Plan *p, int which);
 void tstop(Plan *p, int which);
@@ -135,6 +172,8 @@ void tstop(Plan *p, int which);
 // ----------------------------------------------------------------------------
 // validation + key staging + stable radix sort by z + gather of sorted SoA
 q2d_status sort_and_stage(Plan *p, const void *pos, const void *q, int64_t N);
+// replica batches: sort by (replica, z) into the padded segment layout
+q2d_status sort_and_stage_batch(Plan *p, const void *pos, const void *q);
 
 // device coefficient tables for a list of modes
 q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_pad,
@@ -142,6 +181,10 @@ q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_
 
 // random-batch sampler: writes p->rb_modes and p->rb_coef for P modes
 q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step);
+// replica batches: P modes per replica ([r][2][p_pad], [r][fields][p_pad]);
+// step is read from step_dev when it is not null (captured steps)
+q2d_status sample_modes_batch(Plan *p, int P, uint64_t seed, uint64_t step,
+                              const uint64_t *step_dev);
 
 // k != 0 part over a mode table: per-particle outputs in n_chunks_out chunks
 // of outk, to be summed
@@ -155,6 +198,9 @@ q2d_status k0_run(Plan *p, int64_t N);
 q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0, void *phi,
                     void *F, double *E);
 
+// replica batches: combine, unsort (padding skipped), energy per replica
+q2d_status epilogue_batch(Plan *p, int n_chunks, void *phi, void *F, double *E);
+
 // adjoint: sorted copy of the caller's weights g into s_g
 q2d_status gather_sources(Plan *p, const void *g, int64_t N);
 // adjoint: keep the field of the current sources (charges q) in p->fq
@@ -164,11 +210,24 @@ q2d_status epilogue_field(Plan *p, int64_t N, int n_chunks);
 //   dpos = -(g * field(q) + q * field(g)), unsorted
 q2d_status epilogue_vjp(Plan *p, int64_t N, int n_chunks, double diag, void *dq, void *dpos);
 
+// Enqueue on the plan's internal stream within a scope: the launchers use p->stream.
+struct SideScope {
+    Plan *p;
+    hipStream_t saved;
+    explicit SideScope(Plan *p_) : p(p_), saved(p_->stream) { p->stream = p->side; }
+    ~SideScope() { p->stream = saved; }
+};
+
+// the k = 0 term on the internal stream once the sorted data exist; the main
+// stream must wait for ev_k0 before reading phi0 / fz0
+q2d_status k0_side(Plan *p, int64_t N);
+
 // short range
 q2d_status short_range_run(Plan *p, const void *pos, const void *q, int64_t N, void *phi, void *F,
                            double *E);
 
 }  // namespace q2d
 
-// The opaque handle of the C ABI is the plan itself.
+// The opaque handles of the C ABI are the plan itself.
 struct q2d_plan : public q2d::Plan {};
+struct q2d_batch : public q2d::Plan {};

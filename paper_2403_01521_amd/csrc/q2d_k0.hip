@@ -107,9 +107,14 @@ __global__ __launch_bounds__(128) void k0_sweep(const T *__restrict__ zs,
                                                 double two_pi_over_A,
                                                 const cx<double> *__restrict__ agg,
                                                 double *__restrict__ phi0,
-                                                double *__restrict__ fz0) {
+                                                double *__restrict__ fz0,
+                                                const double *__restrict__ rep_tpa,
+                                                const int32_t *__restrict__ seg_rep,
+                                                int seg_div) {
     const int seg = blockIdx.x * blockDim.x + threadIdx.x;
     if (seg >= nseg) return;
+    // replica batches: 2 pi / A of the replica holding this segment
+    if (rep_tpa) two_pi_over_A = rep_tpa[seg_rep[seg / seg_div]];
     const int64_t i0 = (int64_t)seg * S0;
     const int n = (int)min((int64_t)S0, N - i0);
     double z[S0], q[S0], ph[S0], fz[S0];
@@ -211,6 +216,9 @@ q2d_status k0_run(Plan *p, int64_t N) {
     const void *qsrc = p->src ? p->src : p->s_q.p;
     const double PI = 3.14159265358979323846;
     const double tpa = 2.0 * PI / (p->Lx * p->Ly);
+    const double *rep_tpa = p->R ? (const double *)p->rep_tpa.p : nullptr;
+    const int32_t *seg_rep = p->R ? (const int32_t *)p->seg_rep.p : nullptr;
+    const int seg_div = p->R ? p->S_batch / S0 : 1;
     if (p->fp32)
         k0_agg<float><<<nb, 128, 0, p->stream>>>((const float *)p->s_z.p, (const float *)qsrc,
                                                   N, nseg, p->pp, (cx<double> *)p->agg0.p);
@@ -223,12 +231,12 @@ q2d_status k0_run(Plan *p, int64_t N) {
         k0_sweep<float><<<nb, 128, 0, p->stream>>>(
             (const float *)p->s_z.p, (const float *)qsrc, N, nseg, p->pp, p->c_lin,
             p->k0_self, tpa, (const cx<double> *)p->agg0.p, (double *)p->phi0.p,
-            (double *)p->fz0.p);
+            (double *)p->fz0.p, rep_tpa, seg_rep, seg_div);
     else
         k0_sweep<double><<<nb, 128, 0, p->stream>>>(
             (const double *)p->s_z.p, (const double *)qsrc, N, nseg, p->pp, p->c_lin,
             p->k0_self, tpa, (const cx<double> *)p->agg0.p, (double *)p->phi0.p,
-            (double *)p->fz0.p);
+            (double *)p->fz0.p, rep_tpa, seg_rep, seg_div);
     tstop(p, 3);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }

@@ -23,15 +23,28 @@ namespace q2d {
 
 namespace {
 
+// Replica batches (boxes != null): work-group row blockIdx.y = replica r, with
+// its own box, mode table (modes + r 2 n_pad) and coefficient table
+// (coef + r nf n_pad), and weight (pi/A_r) H_r / P.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mode_coefs(const int32_t *__restrict__ modes, int64_t n,
                                                     int64_t n_pad, const double *weights,
                                                     double weight_const, PairParams pp,
                                                     double alpha, double Lx, double Ly,
-                                                    T *__restrict__ coef) {
+                                                    T *__restrict__ coef,
+                                                    const double *__restrict__ boxes,
+                                                    const double *__restrict__ rep_H, int P) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n_pad) return;
     const int nf = 6 + 4 * pp.mh;
+    if (boxes) {
+        const int r = blockIdx.y;
+        Lx = boxes[3 * r];
+        Ly = boxes[3 * r + 1];
+        weight_const = 3.14159265358979323846 / (Lx * Ly) * rep_H[r] / P;
+        modes += (int64_t)r * 2 * n_pad;
+        coef += (int64_t)r * nf * n_pad;
+    }
     if (m >= n) {
         for (int f = 0; f < nf; ++f) coef[f * n_pad + m] = (T)0;
         return;
@@ -117,15 +130,35 @@ __device__ inline double mh_weight(int mx, int my, double alpha, double Lx, doub
 constexpr int SAMPLER_RESERVE = 64;
 constexpr int SAMPLER_LDS = 2048;  // proposals staged in LDS for the walk
 
-// One block: parallel proposals, then the sequential accept/reject walk.
+// Philox key of replica r of a batch: the batch seed advanced r times by the
+// 64-bit golden-ratio increment (replica 0 draws exactly like one system)
+__host__ __device__ inline uint64_t replica_seed(uint64_t seed, int r) {
+    return seed + (uint64_t)r * 0x9E3779B97F4A7C15ull;
+}
+
+// One block per system: parallel proposals, then the sequential accept/reject
+// walk.  Replica batches (boxes != null): block r uses replica r's box and
+// seed and its own slices of the work arrays and of the mode table.
 __global__ __launch_bounds__(1024) void k_sample(int P, int D, uint64_t seed, uint64_t step,
                                                  double alpha, double Lx, double Ly,
                                                  int32_t *__restrict__ prop,
                                                  double *__restrict__ wgt,
                                                  double *__restrict__ uacc,
                                                  int32_t *__restrict__ modes, int p_pad,
-                                                 int *status) {
+                                                 int *status, const double *__restrict__ boxes,
+                                                 const uint64_t *__restrict__ step_dev) {
     const int n = SAMPLER_RESERVE + P * D;
+    if (step_dev) step = step_dev[0];  // captured step: the number is read on the device
+    if (boxes) {
+        const int r = blockIdx.x;
+        Lx = boxes[3 * r];
+        Ly = boxes[3 * r + 1];
+        seed = replica_seed(seed, r);
+        prop += (int64_t)r * 2 * n;
+        wgt += (int64_t)r * n;
+        uacc += (int64_t)r * n;
+        modes += (int64_t)r * 2 * p_pad;
+    }
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t s0 = (uint32_t)step, s1 = (uint32_t)(step >> 32);
     const double PI = 3.14159265358979323846;
@@ -229,11 +262,11 @@ q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_
     if (p->fp32)
         k_mode_coefs<float><<<nb, 256, 0, p->stream>>>(modes, n, n_pad, weights_dev, weight_const,
                                                        p->pp, p->alpha, p->Lx, p->Ly,
-                                                       (float *)coef);
+                                                       (float *)coef, nullptr, nullptr, 0);
     else
         k_mode_coefs<double><<<nb, 256, 0, p->stream>>>(modes, n, n_pad, weights_dev,
                                                         weight_const, p->pp, p->alpha, p->Lx,
-                                                        p->Ly, (double *)coef);
+                                                        p->Ly, (double *)coef, nullptr, nullptr, 0);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
@@ -252,11 +285,47 @@ q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step) {
     double *wgt = (double *)((char *)p->rb_work.p + (size_t)n * 2 * sizeof(int32_t));
     double *uacc = wgt + n;
     k_sample<<<1, 1024, 0, p->stream>>>(P, D, seed, step, p->alpha, p->Lx, p->Ly, prop, wgt, uacc,
-                                         (int32_t *)p->rb_modes.p, p_pad, (int *)p->status.p);
+                                         (int32_t *)p->rb_modes.p, p_pad, (int *)p->status.p,
+                                         nullptr, nullptr);
     if (hipGetLastError() != hipSuccess) return Q2D_EDEVICE;
     const double PI = 3.14159265358979323846;
     return build_mode_coefs(p, (const int32_t *)p->rb_modes.p, P, p_pad, nullptr,
                             PI / (p->Lx * p->Ly) * p->H / P, p->rb_coef.p);
+}
+
+q2d_status sample_modes_batch(Plan *p, int P, uint64_t seed, uint64_t step,
+                              const uint64_t *step_dev) {
+    const int D = p->opts.thin > 0 ? p->opts.thin : 1;
+    const int n = SAMPLER_RESERVE + P * D;
+    const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
+    const int nf = coef_fields(p->mh);
+    const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+    q2d_status st;
+    if ((st = ensure(p, p->rb_work,
+                     (size_t)p->R * n * (2 * sizeof(int32_t) + 2 * sizeof(double)))) != Q2D_OK)
+        return st;
+    if ((st = ensure(p, p->rb_modes, (size_t)p->R * 2 * p_pad * sizeof(int32_t))) != Q2D_OK)
+        return st;
+    if ((st = ensure(p, p->rb_coef, (size_t)p->R * nf * p_pad * tsz)) != Q2D_OK) return st;
+    int32_t *prop = (int32_t *)p->rb_work.p;
+    double *wgt = (double *)((char *)p->rb_work.p + (size_t)p->R * n * 2 * sizeof(int32_t));
+    double *uacc = wgt + (size_t)p->R * n;
+    const double *boxes = (const double *)p->rep_box.p;
+    k_sample<<<p->R, 1024, 0, p->stream>>>(P, D, seed, step, p->alpha, 0.0, 0.0, prop, wgt, uacc,
+                                            (int32_t *)p->rb_modes.p, p_pad, (int *)p->status.p,
+                                            boxes, step_dev);
+    const dim3 grid((p_pad + 255) / 256, p->R);
+    if (p->fp32)
+        k_mode_coefs<float><<<grid, 256, 0, p->stream>>>(
+            (const int32_t *)p->rb_modes.p, P, p_pad, nullptr, 0.0, p->pp, p->alpha, 0.0, 0.0,
+            (float *)p->rb_coef.p, boxes, (const double *)p->rep_H.p, P);
+    else
+        k_mode_coefs<double><<<grid, 256, 0, p->stream>>>(
+            (const int32_t *)p->rb_modes.p, P, p_pad, nullptr, 0.0, p->pp, p->alpha, 0.0, 0.0,
+            (double *)p->rb_coef.p, boxes, (const double *)p->rep_H.p, P);
+    p->rep_mstride = 2 * (int64_t)p_pad;
+    p->rep_cstride = (int64_t)nf * p_pad;
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
 }  // namespace q2d

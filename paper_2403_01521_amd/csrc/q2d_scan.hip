@@ -140,6 +140,10 @@ struct KArgs {
     int nmodes, gpad;
     int nunits;
     Unit units[MAX_UNITS];
+    // replica batches: replica of each segment, and the distance between two
+    // replicas' mode and coefficient tables (null / 0 for one system)
+    const int32_t *seg_rep;
+    int64_t rep_mstride, rep_cstride;
     T bre[MAX_PAIRS], bim[MAX_PAIRS];
     cx<T> *agg;  // [2 dirs][nseg][MH+1 slots][2 inputs][gpad]
     T *outk;     // [chunks][N][4]
@@ -161,6 +165,7 @@ struct LaneMap {
     int f, mi, seg;
     int64_t i0;  // first particle of this lane's segment
     int n;       // its length (0 if past the last segment)
+    int64_t mb, cb;  // offsets of the segment's replica in the mode / coefficient tables
 };
 
 template <typename T>
@@ -178,6 +183,9 @@ __device__ inline LaneMap lane_map(const KArgs<T> &a) {
     r.seg = r.wave * r.u.F + r.f;
     r.i0 = (int64_t)r.seg * a.S;
     r.n = r.seg < a.nseg ? (int)(min(r.i0 + (int64_t)a.S, a.N) - r.i0) : 0;
+    const int rep = (a.seg_rep && r.seg < a.nseg) ? a.seg_rep[r.seg] : 0;
+    r.mb = (int64_t)rep * a.rep_mstride;
+    r.cb = (int64_t)rep * a.rep_cstride;
     return r;
 }
 
@@ -203,9 +211,9 @@ __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
         const int ml = g * lm.wb + lm.mi;
         const bool mv = ml < lm.u.nm;
         const int m = lm.u.m0 + ml;
-        const int mx = mv ? a.modes[a.moff + m] : 0;
-        const int my = mv ? a.modes[a.mstride + a.moff + m] : 0;
-        const T k = mv ? a.coef[2 * a.cstride + a.moff + m] : (T)0;
+        const int mx = mv ? a.modes[lm.mb + a.moff + m] : 0;
+        const int my = mv ? a.modes[lm.mb + a.mstride + a.moff + m] : 0;
+        const T k = mv ? a.coef[lm.cb + 2 * a.cstride + a.moff + m] : (T)0;
         cx<T> fx[MH], fy[MH], bx[MH], by[MH];
 #pragma unroll
         for (int l = 0; l < MH; ++l) fx[l] = fy[l] = bx[l] = by[l] = cx<T>{0, 0};
@@ -488,9 +496,11 @@ __global__ __launch_bounds__(64) void k_sweep(const KArgs<T> a) {
         const int ml = g * lm.wb + lm.mi;
         const bool mv = ml < lm.u.nm;
         const int m = lm.u.m0 + ml;
-        auto ld = [&](int f) -> T { return mv ? a.coef[(int64_t)f * a.cstride + a.moff + m] : (T)0; };
-        const int mx = mv ? a.modes[a.moff + m] : 0;
-        const int my = mv ? a.modes[a.mstride + a.moff + m] : 0;
+        auto ld = [&](int f) -> T {
+            return mv ? a.coef[lm.cb + (int64_t)f * a.cstride + a.moff + m] : (T)0;
+        };
+        const int mx = mv ? a.modes[lm.mb + a.moff + m] : 0;
+        const int my = mv ? a.modes[lm.mb + a.mstride + a.moff + m] : 0;
         const T om = ld(3);
         SweepCoef<T, MH> cf;
         cf.kx = ld(0);
@@ -525,6 +535,11 @@ struct CArgs {
     cx<T> *agg;               // [2][nseg][ncols]
     const T *coef;
     int64_t cstride, moff;
+    // replica batches: replica of carry segment s is seg_rep[s / seg_div]; no
+    // carry crosses from one replica to the next (null for one system)
+    const int32_t *seg_rep;
+    int seg_div;
+    int64_t rep_cstride;
 };
 
 constexpr int CAR_L = 8;       // segments per range
@@ -537,35 +552,53 @@ __device__ inline void compose(cx<double> &c2, cx<double> &D2, cx<double> c1, cx
     D2 = cmul(D2, D1);
 }
 
+template <typename T>
+__device__ inline int carry_rep(const CArgs<T> &a, int s) {
+    return a.seg_rep ? a.seg_rep[s / a.seg_div] : 0;
+}
+
+// true if segment s is the last one of its system (no gap to a next segment)
+template <typename T>
+__device__ inline bool carry_last(const CArgs<T> &a, int s) {
+    return s + 1 >= a.nseg || (a.seg_rep && carry_rep(a, s + 1) != carry_rep(a, s));
+}
+
 // Decay factors of segment s for a column: W_s = e^{-beta (z_last - z_first)}
-// inside the segment and G_s = e^{-beta (z_first(s+1) - z_last(s))} across the gap.
+// inside the segment and G_s = e^{-beta (z_first(s+1) - z_last(s))} across the
+// gap (0 after the last segment of a replica: its carries stop there).
 template <typename T, bool KMODE>
 struct Decay {
     const CArgs<T> &a;
-    int slot;
+    int slot, mode;
     bool pair;
     double kk;
     __device__ Decay(const CArgs<T> &a_, int col) : a(a_) {
         slot = col / (2 * a.gpad);
-        const int mode = col % a.gpad;
+        mode = col % a.gpad;
         pair = slot < a.mh;
         kk = 0.0;
-        if (KMODE && !pair && mode < a.nmodes) kk = (double)a.coef[2 * a.cstride + a.moff + mode];
+        if (KMODE && !pair && mode < a.nmodes && !a.seg_rep)
+            kk = (double)a.coef[2 * a.cstride + a.moff + mode];
     }
     __device__ void get(int s, cx<double> &W, cx<double> &G) const {
         if (pair) {
             W = a.spans[((int64_t)s * a.mh + slot) * 2];
             G = a.spans[((int64_t)s * a.mh + slot) * 2 + 1];
         } else if (KMODE) {
+            double k = kk;
+            if (a.seg_rep && mode < a.nmodes)
+                k = (double)a.coef[(int64_t)carry_rep(a, s) * a.rep_cstride + 2 * a.cstride +
+                                   a.moff + mode];
             const int64_t b = (int64_t)s * a.S, e = min(b + (int64_t)a.S, a.N) - 1;
             const double zf = (double)a.z[b], zl = (double)a.z[e];
             const double zn = (s + 1 < a.nseg) ? (double)a.z[(int64_t)(s + 1) * a.S] : zl;
-            W = cx<double>{exp(-kk * (zl - zf)), 0.0};
-            G = cx<double>{exp(-kk * (zn - zl)), 0.0};
+            W = cx<double>{exp(-k * (zl - zf)), 0.0};
+            G = cx<double>{exp(-k * (zn - zl)), 0.0};
         } else {
             W = cx<double>{1.0, 0.0};
             G = cx<double>{1.0, 0.0};
         }
+        if (a.seg_rep && carry_last(a, s)) G = cx<double>{0.0, 0.0};
     }
     // factors of one step in direction dir: forward (W_s, G_s); backward
     // (W_s, G_{s-1}), the gap below s (none below segment 0)
@@ -719,6 +752,8 @@ q2d_status carry_run(Plan *p, const CArgs<T> &ca, Buf &tmp) {
 }
 
 // per (segment, pair): W = e^{-beta (z_last - z_first)}, G = e^{-beta (z_next_first - z_last)}
+// (the spans tables of pair slots; G of a replica's last segment is replaced
+// by 0 where the carry walk reads it)
 template <typename T>
 __global__ __launch_bounds__(256) void k_spans(const T *__restrict__ z, int64_t N, int S, int nseg,
                                                PairParams pp, cx<double> *__restrict__ spans) {
@@ -802,9 +837,11 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
     using U = typename Tr<T>::U;
     *nchunks_out = 0;
     if (nmodes <= 0 || N <= 0) return Q2D_OK;
-    const int S = choose_S(N);
+    // a replica batch fixes S: its particles are laid out in whole segments
+    const int S = p->R ? p->S_batch : choose_S(N);
     const int nseg = (int)((N + S - 1) / S);
     const int mh = p->mh;
+    const int32_t *seg_rep = p->R ? (const int32_t *)p->seg_rep.p : nullptr;
     const int64_t MB = ((int64_t)std::max(env_int("Q2D_MODE_BATCH", 1024), 1) + WAVE - 1) / WAVE * WAVE;
     const int64_t nfull = (nmodes / WAVE) * WAVE;
     const int rem = (int)(nmodes - nfull);
@@ -856,6 +893,9 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
     }
     ka.agg = (cx<T> *)p->agg.p;
     ka.outk = (T *)p->outk.p;
+    ka.seg_rep = seg_rep;
+    ka.rep_mstride = p->R ? p->rep_mstride : 0;
+    ka.rep_cstride = p->R ? p->rep_cstride : 0;
     for (int bi = 0; bi < nbatch; ++bi) {
         const int64_t b0 = (int64_t)bi * MB;
         const int nbf = (int)std::max<int64_t>(0, std::min(MB, nfull - b0));
@@ -902,6 +942,9 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         ca.coef = ka.coef;
         ca.cstride = cstride;
         ca.moff = ka.moff;
+        ca.seg_rep = seg_rep;
+        ca.seg_div = 1;
+        ca.rep_cstride = ka.rep_cstride;
         if ((st = carry_run<T, true>(p, ca, p->carry_tmp)) != Q2D_OK) return st;
         tstart(p, 0);
         dispatch_sweep<T>(p, ka, dim3(blocks));
@@ -935,6 +978,11 @@ q2d_status carry_k0(Plan *p, int nseg, int S, int64_t N) {
     ca.spans = (const cx<double> *)p->spans0.p;
     ca.agg = (cx<double> *)p->agg0.p;
     ca.coef = nullptr;
+    if (p->R) {
+        // k = 0 segments of S particles lie inside the batch's segments
+        ca.seg_rep = (const int32_t *)p->seg_rep.p;
+        ca.seg_div = p->S_batch / S;
+    }
     return carry_run<double, false>(p, ca, p->carry_tmp0);
 }
 

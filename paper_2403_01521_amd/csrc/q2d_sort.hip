@@ -272,7 +272,178 @@ q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
+// ---------------------------------------------------------------------------
+// replica batches: sort by (replica, z), then lay each replica out in whole
+// segments of S particles; the slots after its last particle are padding
+// (zero charge at the replica's top height, input index -1)
+// ---------------------------------------------------------------------------
+template <typename T, typename K>
+__global__ __launch_bounds__(256) void k_stage_batch(const T *__restrict__ pos,
+                                                     const T *__restrict__ q, int64_t N,
+                                                     const int32_t *__restrict__ rep_of,
+                                                     const double *__restrict__ boxes,
+                                                     K *__restrict__ keys, int32_t *__restrict__ vals,
+                                                     int validate, int *status,
+                                                     double *__restrict__ qsums) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const T z = pos[3 * i + 2];
+    keys[i] = zkey(z);
+    vals[i] = (int32_t)i;
+    if (validate) {
+        const int r = rep_of[i];
+        const T x = pos[3 * i], y = pos[3 * i + 1];
+        const double qv = (double)q[i];
+        const bool finite = isfinite((double)x) && isfinite((double)y) && isfinite((double)z) &&
+                            isfinite(qv);
+        if (!finite || !((double)z >= 0.0 && (double)z <= boxes[3 * r + 2]))
+            set_status(status, Q2D_EOUTOFBOX);
+        atomicAdd(&qsums[2 * r], qv);
+        atomicAdd(&qsums[2 * r + 1], fabs(qv));
+    }
+}
+
+__global__ void k_zero_sums(double *a, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0;
+}
+
+__global__ void k_neutral_batch(const double *qsums, int R, int *status) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R && fabs(qsums[2 * r]) > 1e-6 * qsums[2 * r + 1] + 1e-300)
+        atomicOr(status, 1 << Q2D_ENONNEUTRAL);
+}
+
+// second key: replica of the element now at position i (bits `shift` and up)
+__global__ __launch_bounds__(256) void k_repkey(const int32_t *__restrict__ vals, int64_t N,
+                                                const int32_t *__restrict__ rep_of,
+                                                uint32_t *__restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) keys[i] = (uint32_t)rep_of[vals[i]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_batch(
+    const T *__restrict__ pos, const T *__restrict__ q, const int32_t *__restrict__ perm, int64_t N,
+    const int32_t *__restrict__ rep_of, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ poff, const double *__restrict__ boxes,
+    typename Fix<T>::U *__restrict__ ux, typename Fix<T>::U *__restrict__ uy, T *__restrict__ zs,
+    T *__restrict__ qs, int32_t *__restrict__ pperm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t o = perm[i];
+    const int r = rep_of[o];
+    const int64_t pi = poff[r] + (i - off[r]);
+    ux[pi] = Fix<T>::frac((double)pos[3 * (int64_t)o] / boxes[3 * r]);
+    uy[pi] = Fix<T>::frac((double)pos[3 * (int64_t)o + 1] / boxes[3 * r + 1]);
+    zs[pi] = pos[3 * (int64_t)o + 2] + (T)0;
+    qs[pi] = q[o];
+    pperm[pi] = o;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_batch(int64_t Npad, int S,
+                                                   const int32_t *__restrict__ seg_rep,
+                                                   const int64_t *__restrict__ off,
+                                                   const int64_t *__restrict__ poff,
+                                                   typename Fix<T>::U *__restrict__ ux,
+                                                   typename Fix<T>::U *__restrict__ uy,
+                                                   T *__restrict__ zs, T *__restrict__ qs,
+                                                   int32_t *__restrict__ pperm) {
+    const int64_t pi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pi >= Npad) return;
+    const int r = seg_rep[pi / S];
+    const int64_t n = off[r + 1] - off[r];
+    if (pi - poff[r] < n) return;
+    // a replica with padding has at least one particle: its top height
+    ux[pi] = 0;
+    uy[pi] = 0;
+    zs[pi] = zs[poff[r] + n - 1];
+    qs[pi] = (T)0;
+    pperm[pi] = -1;
+}
+
+template <typename T, typename K>
+q2d_status sort_batch_impl(Plan *p, const void *pos_v, const void *q_v) {
+    const T *pos = (const T *)pos_v;
+    const T *q = (const T *)q_v;
+    using U = typename Fix<T>::U;
+    const int64_t N = p->Ntot, Npad = p->Npad;
+    q2d_status st;
+    if ((st = ensure(p, p->keys_a, N * sizeof(K))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->keys_b, N * sizeof(K))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->vals_a, N * sizeof(int32_t))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->vals_b, N * sizeof(int32_t))) != Q2D_OK) return st;
+    const int ntiles = (int)((N + SORT_TILE - 1) / SORT_TILE);
+    if ((st = ensure(p, p->hist, ((size_t)256 * ntiles + 256) * sizeof(uint32_t))) != Q2D_OK)
+        return st;
+    if ((st = ensure(p, p->s_ux, Npad * sizeof(U))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->s_uy, Npad * sizeof(U))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->s_z, Npad * sizeof(T))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->s_q, Npad * sizeof(T))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->pperm, Npad * sizeof(int32_t))) != Q2D_OK) return st;
+    int *status = (int *)p->status.p;
+    // per-replica sums of q and |q| follow H in the same buffer ([R] + [R][2])
+    double *qsums = (double *)p->rep_H.p + p->R;
+    const int nb = (int)((N + 255) / 256);
+    const int32_t *rep_of = (const int32_t *)p->rep_of.p;
+    const double *boxes = (const double *)p->rep_box.p;
+    if (p->opts.validate)
+        k_zero_sums<<<(2 * p->R + 255) / 256, 256, 0, p->stream>>>(qsums, 2 * p->R);
+    if (N > 0)
+        k_stage_batch<T, K><<<nb, 256, 0, p->stream>>>(pos, q, N, rep_of, boxes, (K *)p->keys_a.p,
+                                                       (int32_t *)p->vals_a.p, p->opts.validate,
+                                                       status, qsums);
+    if (p->opts.validate)
+        k_neutral_batch<<<(p->R + 255) / 256, 256, 0, p->stream>>>(qsums, p->R, status);
+    uint32_t *hist = (uint32_t *)p->hist.p;
+    uint32_t *tot = hist + (size_t)256 * ntiles;
+    K *kin = (K *)p->keys_a.p, *kout = (K *)p->keys_b.p;
+    int32_t *vin = (int32_t *)p->vals_a.p, *vout = (int32_t *)p->vals_b.p;
+    if (N > 0) {
+        // least significant first: z (all its bytes), then the replica index
+        for (int pass = 0; pass < (int)sizeof(K); ++pass) {
+            k_hist<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, N, 8 * pass, hist, ntiles);
+            k_scan_digit<<<256, 256, 0, p->stream>>>(hist, ntiles, tot);
+            k_scatter<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, vin, kout, vout, N, 8 * pass,
+                                                                hist, tot, ntiles);
+            std::swap(kin, kout);
+            std::swap(vin, vout);
+        }
+        uint32_t *rin = (uint32_t *)kin, *rout = (uint32_t *)kout;
+        k_repkey<<<nb, 256, 0, p->stream>>>(vin, N, rep_of, rin);
+        const int rpasses = p->R > 256 ? 2 : 1;
+        for (int pass = 0; pass < rpasses; ++pass) {
+            k_hist<uint32_t><<<ntiles, SORT_THREADS, 0, p->stream>>>(rin, N, 8 * pass, hist, ntiles);
+            k_scan_digit<<<256, 256, 0, p->stream>>>(hist, ntiles, tot);
+            k_scatter<uint32_t><<<ntiles, SORT_THREADS, 0, p->stream>>>(rin, vin, rout, vout, N,
+                                                                       8 * pass, hist, tot, ntiles);
+            std::swap(rin, rout);
+            std::swap(vin, vout);
+        }
+        p->perm = vin;
+        k_gather_batch<T><<<nb, 256, 0, p->stream>>>(
+            pos, q, vin, N, rep_of, (const int64_t *)p->rep_off.p, (const int64_t *)p->rep_poff.p,
+            boxes, (U *)p->s_ux.p, (U *)p->s_uy.p, (T *)p->s_z.p, (T *)p->s_q.p,
+            (int32_t *)p->pperm.p);
+    }
+    if (Npad > N)
+        k_pad_batch<T><<<(int)((Npad + 255) / 256), 256, 0, p->stream>>>(
+            Npad, p->S_batch, (const int32_t *)p->seg_rep.p, (const int64_t *)p->rep_off.p,
+            (const int64_t *)p->rep_poff.p, (U *)p->s_ux.p, (U *)p->s_uy.p, (T *)p->s_z.p,
+            (T *)p->s_q.p, (int32_t *)p->pperm.p);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
 }  // namespace
+
+q2d_status sort_and_stage_batch(Plan *p, const void *pos, const void *q) {
+    tstart(p, 2);
+    q2d_status st = p->fp32 ? sort_batch_impl<float, uint32_t>(p, pos, q)
+                            : sort_batch_impl<double, uint64_t>(p, pos, q);
+    tstop(p, 2);
+    return st;
+}
 
 q2d_status gather_sources(Plan *p, const void *g, int64_t N) {
     const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);

@@ -97,7 +97,33 @@ CONFIGS = {
     2: dict(name="exactk_N1e4", box=(60.0, 60.0, 10.0), alpha=0.25, rc=None, kc=1.6, M=24),
     3: dict(name="rbm_N1e6", box=(600.0, 600.0, 10.0), alpha=0.1, rc=None, kc=None, M=16, P=100),
     4: dict(name="grad_N1e5", box=(200.0, 200.0, 8.0), alpha=0.25, rc=None, kc=1.6, M=24),
+    5: dict(name="replicas_R256", R=256, n_range=(1000, 20000), Lz=6.0, density=0.05,
+            L_range=(30.0, 150.0), alpha=0.3, M=16, P=64),
 }
+
+
+def make_replicas(R=None, n_range=None, dtype=np.float64):
+    """Configuration 5: R independent +-1 systems, N_r log-uniform in n_range
+    (rounded to even), Lx = Ly = clamp(sqrt(N_r / (density Lz)), L_range),
+    uniform in [0, L)^2 x [0, Lz].  Returns dict(pos, q (concatenated by
+    replica), boxes (R x 3), counts, alpha, M, P)."""
+    c = dict(CONFIGS[5])
+    rng = rng_for(5)
+    R = R or c["R"]
+    lo, hi = n_range or c["n_range"]
+    counts = np.exp(rng.uniform(np.log(lo), np.log(hi), R))
+    counts = (2 * np.round(counts / 2)).astype(np.int64)
+    Lz = c["Lz"]
+    L = np.clip(np.sqrt(counts / (c["density"] * Lz)), *c["L_range"])
+    boxes = np.stack([L, L, np.full(R, Lz)], axis=1)
+    pos, q = [], []
+    for r in range(R):
+        p, qq = uniform_ions(rng, counts[r] // 2, counts[r] // 2, tuple(boxes[r]))
+        pos.append(p)
+        q.append(qq)
+    c.update(pos=np.concatenate(pos).astype(dtype), q=np.concatenate(q).astype(dtype),
+             boxes=boxes, counts=counts, R=R)
+    return c
 
 
 def make_config(idx, dtype=np.float64, n_override=None):
