@@ -21,10 +21,12 @@ the FP64 path on the same GPU and the FP32/FP64 speedup, the relative RMS
 difference of FP32 and FP64 forces for identical modes, the FP64 exact-k SOE
 sum over all 42,184 modes with e^{-k^2/4 alpha^2} >= 1e-16 (time, and as the
 reference of the random-batch force error per draw and of the running mean over
-the K draws), and the oracle on all host cores.
+the K draws), the oracle on all host cores, and the 256-replica batch of
+configuration 5 (aggregate and per-replica evaluations/s, eager and replayed
+as a hipGraph, against one single-system call per replica).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
-                       [--no-exact]
+                       [--no-exact] [--no-replicas]
 """
 
 import argparse
@@ -146,6 +148,66 @@ def cpu_baseline(c, w, s, modes):
                 host_cpu=_cpu_model(), host_threads=nthr)
 
 
+def replicas_report(w, s, steps):
+    """Configuration 5: 256 replicas of uneven N (log-uniform 1e3..2e4), P = 64,
+    FP32, one batch step per call; eager calls and graph replays, against the
+    same work done by one single-system call per replica."""
+    import torch
+    import paper_2403_01521_amd as q2d
+    import workloads as wl
+    c = wl.make_replicas(dtype=np.float32)
+    P = c["P"]
+    counts, boxes = c["counts"], c["boxes"]
+    pos = torch.tensor(c["pos"], device="cuda")
+    q = torch.tensor(c["q"], device="cuda")
+    b = q2d.Batch(boxes, counts, c["alpha"], w, s, precision="fp32", p_max=P)
+    S = b.tune(pos, q, P, seed=SEED)
+    for i in range(3):
+        b.rbm_step(pos, q, P, SEED, 1000 + i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        b.rbm_step(pos, q, P, SEED, i)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / steps
+    b.capture(pos, q, P, SEED, 0)
+    b.replay(3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.replay(steps)
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+    b.close()
+    # the same replicas one call each
+    off = np.concatenate([[0], np.cumsum(counts)])
+    plans = [q2d.Plan(boxes[r], c["alpha"], w, s, precision="fp32", n_max=int(counts[r]), p_max=P)
+             for r in range(len(counts))]
+    views = [(pos[off[r]:off[r + 1]], q[off[r]:off[r + 1]]) for r in range(len(counts))]
+    for r, pl in enumerate(plans):
+        pl.rbm_step(views[r][0], views[r][1], P, q2d.replica_seed(SEED, r), 0)
+    torch.cuda.synchronize()
+    ns = max(2, steps // 10)
+    t0 = time.perf_counter()
+    for i in range(ns):
+        for r, pl in enumerate(plans):
+            pl.rbm_step(views[r][0], views[r][1], P, q2d.replica_seed(SEED, r), i)
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3 / ns
+    for pl in plans:
+        pl.close()
+    Ntot = int(counts.sum())
+    best = min(ms_eager, ms_graph)
+    per = counts / (best * 1e-3)
+    return {"workload": "256 replicas, N log-uniform [1e3, 2e4] (total %d), Lx=Ly=clamp(sqrt(N/0.3),"
+                        "30,150), Lz=6, alpha=0.3, P=64, M=16, FP32" % Ntot,
+            "segment": S, "ms_per_step_eager": ms_eager, "ms_per_step_graph": ms_graph,
+            "aggregate_evals_per_s": Ntot / (best * 1e-3),
+            "per_replica_evals_per_s": {"min": float(per.min()), "median": float(np.median(per)),
+                                        "max": float(per.max())},
+            "sequential_single_plans_ms": ms_seq,
+            "batch_speedup_vs_sequential": ms_seq / best}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -194,6 +256,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the FP64 exact-k reference (time and random-batch error)")
+    ap.add_argument("--no-replicas", action="store_true",
+                    help="skip the 256-replica batch (configuration 5) report")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -331,6 +395,9 @@ def main():
         res["fp64_value"] = N / (ms64 * 1e-3)
         res["fp32_over_fp64_speedup"] = ms64 / ms
         res["fp32_vs_fp64_force_rel_rms"] = rel(F32.double(), F64)
+    if not args.no_replicas:
+        log("256-replica batch (configuration 5)")
+        res["replicas"] = replicas_report(w, s, max(10, args.steps // 5))
     if not args.no_cpu:
         log("oracle timing on the host")
         res["cpu_baseline"] = cpu_baseline(c32, w, s, r32_modes)
