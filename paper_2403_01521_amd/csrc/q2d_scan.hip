@@ -976,12 +976,14 @@ __global__ __launch_bounds__(256) void k_cfold(const CArgs<T> a, int nr, cx<doub
     }
 }
 
-// (2) one work-group per column: exclusive scan of the range transfers in the
-// direction of propagation; leaves the carry into each range in rc[.].c
-__global__ __launch_bounds__(256) void k_cscan(int ncols, int nr, cx<double> *rc) {
-    __shared__ cx<double> sc[256], sd[256];
+// (2) one work-group of NT threads per column: exclusive scan of the range
+// transfers in the direction of propagation; leaves the carry into each range
+// in rc[.].c (NT = 1024 for long columns keeps each thread's serial part short)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_cscan(int ncols, int nr, cx<double> *rc) {
+    __shared__ cx<double> sc[NT], sd[NT];
     const int col = blockIdx.x, t = threadIdx.x;
-    const int per = (nr + 255) / 256;
+    const int per = (nr + NT - 1) / NT;
     for (int dir = 0; dir < 2; ++dir) {
         cx<double> *base = rc + ((int64_t)dir * ncols + col) * nr * 2;
         // thread t owns propagation positions [t*per, (t+1)*per)
@@ -1000,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_cscan(int ncols, int nr, cx<double> *rc
         sc[t] = c;
         sd[t] = D;
         __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
+        for (int off = 1; off < NT; off <<= 1) {
             cx<double> pc{0.0, 0.0}, pd{1.0, 0.0};
             const bool has = t >= off;
             if (has) {
@@ -1054,7 +1056,10 @@ q2d_status carry_run(Plan *p, const CArgs<T> &ca, Buf &tmp) {
     const int64_t nt = (int64_t)ca.ncols * nr;
     const int nb = (int)((nt + 255) / 256);
     k_cfold<T, KMODE><<<nb, 256, 0, p->stream>>>(ca, nr, rc);
-    k_cscan<<<ca.ncols, 256, 0, p->stream>>>(ca.ncols, nr, rc);
+    if (nr > 1024)
+        k_cscan<1024><<<ca.ncols, 1024, 0, p->stream>>>(ca.ncols, nr, rc);
+    else
+        k_cscan<256><<<ca.ncols, 256, 0, p->stream>>>(ca.ncols, nr, rc);
     k_capply<T, KMODE><<<nb, 256, 0, p->stream>>>(ca, nr, rc);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
