@@ -40,6 +40,11 @@ q2d_status ensure(Plan *p, Buf &b, size_t bytes) {
     return Q2D_OK;
 }
 
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return (v && *v) ? atoi(v) : dflt;
+}
+
 void tstart(Plan *p, int which) {
     if (!(p->timing & (1 << which))) return;
     hipEvent_t e;
@@ -311,6 +316,7 @@ q2d_status plan_init(Plan *p, double Lx, double Ly, double Lz, double alpha, dou
     if (p->opts.thin <= 0) p->opts.thin = 1;
     p->fp32 = opts->precision == Q2D_FP32;
     p->stream = (hipStream_t)stream;
+    p->serial = env_int("Q2D_SERIAL", 0) != 0;
     if (hipGetDevice(&p->device) != hipSuccess) return Q2D_EDEVICE;
     if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||

@@ -144,6 +144,9 @@ struct Plan {
 
     // timing
     int timing = 0;  // bit mask of timed kernel families
+    // Q2D_SERIAL=1 at plan creation: the side-stream work runs on the caller's
+    // stream (no overlap; for per-kernel profiles)
+    bool serial = false;
     hipEvent_t ev[5][2]{};
     double t_ms[5]{};
     int64_t t_cnt[5]{};
@@ -162,6 +165,9 @@ void plan_release(Plan *p);
 q2d_status plan_check(Plan *p);
 // H and the random-batch j = i constant of a box for the plan's SOE table
 void box_constants(const Plan *p, double Lx, double Ly, double *H, double *diag_rb);
+
+// integer from the environment (tuning switches), dflt if unset
+int env_int(const char *name, int dflt);
 
 // timing helpers
 void tstart(Plan *p, int which);
@@ -214,7 +220,9 @@ q2d_status epilogue_vjp(Plan *p, int64_t N, int n_chunks, double diag, void *dq,
 struct SideScope {
     Plan *p;
     hipStream_t saved;
-    explicit SideScope(Plan *p_) : p(p_), saved(p_->stream) { p->stream = p->side; }
+    explicit SideScope(Plan *p_) : p(p_), saved(p_->stream) {
+        if (!p->serial) p->stream = p->side;
+    }
     ~SideScope() { p->stream = saved; }
 };
 

@@ -12,9 +12,15 @@
 // sources, q_j and q_j z_j; the linear terms are the beta = 0 scans (prefix
 // sums).  Conjugate SOE terms are carried once with doubled coefficients.
 //
-// Layout: one thread per segment of S0 consecutive sorted particles holding
-// all SOE pairs; segment aggregates and carries use the same FP64 carry scan
-// as the k != 0 modes.
+// Layout: segments of S0 = 64 consecutive sorted particles (S0 divides every
+// replica-batch segment, so no k = 0 segment straddles two replicas).  A lane
+// works on one (segment, pair): a wave holds 64 / LG segments of LG pair
+// lanes each (LG = 8 for up to 8 pairs, else 16), the segment's heights and
+// sources staged in LDS and read as broadcasts.  The linear (beta = 0) terms
+// ride along on pair lane 0.  Per-particle sums over the pairs use a register
+// reduce-scatter inside each lane group (every LG steps, fixed order), so the
+// results are deterministic.  Segment aggregates and carries use the same
+// FP64 carry scan as the k != 0 modes.
 #include "q2d_internal.h"
 
 namespace q2d {
@@ -24,7 +30,8 @@ q2d_status spans_k0(Plan *p, int nseg, int S, int64_t N);
 
 namespace {
 
-constexpr int S0 = 16;
+constexpr int S0 = 64;
+constexpr int ZP = S0 + 1;  // padded LDS rows: the segment groups hit distinct banks
 
 __device__ inline cx<double> cexpm64(double br, double bi, double t) {
     const double ar = br * t, ai = bi * t;
@@ -50,111 +57,179 @@ __device__ inline int64_t a0_idx(int nseg, int ns, int dir, int seg, int slot, i
     return (((int64_t)dir * nseg + seg) * ns + slot) * 2 + inp;
 }
 
-template <typename T>
-__global__ __launch_bounds__(128) void k0_agg(const T *__restrict__ zs, const T *__restrict__ qs,
-                                              int64_t N, int nseg, PairParams pp,
-                                              cx<double> *__restrict__ agg) {
-    const int seg = blockIdx.x * blockDim.x + threadIdx.x;
-    if (seg >= nseg) return;
-    const int64_t i0 = (int64_t)seg * S0;
-    const int n = (int)min((int64_t)S0, N - i0);
-    double z[S0], q[S0];
-#pragma unroll
-    for (int j = 0; j < S0; ++j) {
-        z[j] = j < n ? (double)zs[i0 + j] : 0.0;
-        q[j] = j < n ? (double)qs[i0 + j] : 0.0;
+template <int LG>
+struct K0Lds {
+    static constexpr int G = WAVE / LG;  // segments per wave
+    double z[G][ZP], q[G][ZP];
+    double ph[G][ZP], fz[G][ZP];
+};
+
+// heights and sources of the wave's segments (zero past N)
+template <typename T, int LG>
+__device__ inline void k0_stage(const T *__restrict__ zs, const T *__restrict__ qs, int64_t N,
+                                int seg0, K0Lds<LG> &L) {
+    constexpr int G = K0Lds<LG>::G;
+    for (int e = threadIdx.x; e < G * S0; e += WAVE) {
+        const int g = e / S0, j = e % S0;
+        const int64_t i = (int64_t)(seg0 + g) * S0 + j;
+        L.z[g][j] = i < N ? (double)zs[i] : 0.0;
+        L.q[g][j] = i < N ? (double)qs[i] : 0.0;
     }
+    __syncthreads();
+}
+
+// Sum v[t] over the LG lanes of a group; lane l of the group gets the sum for
+// t = l.  Level h: lanes with bit h set keep the upper half of what is left
+// and pass the lower half to their partner l ^ h.
+template <int LG>
+__device__ inline double group_reduce_scatter(double (&v)[LG], int l) {
+#pragma unroll
+    for (int h = LG / 2; h >= 1; h >>= 1) {
+        const bool hi = (l & h) != 0;
+#pragma unroll
+        for (int t = 0; t < h; ++t) {
+            const double keep = hi ? v[t + h] : v[t];
+            const double send = hi ? v[t] : v[t + h];
+            v[t] = keep + __shfl_xor(send, h);
+        }
+    }
+    return v[0];
+}
+
+template <typename T, int LG>
+__global__ __launch_bounds__(WAVE) void k0_agg(const T *__restrict__ zs, const T *__restrict__ qs,
+                                               int64_t N, int nseg, PairParams pp,
+                                               cx<double> *__restrict__ agg) {
+    constexpr int G = K0Lds<LG>::G;
+    __shared__ K0Lds<LG> L;
+    const int g = threadIdx.x / LG, l = threadIdx.x % LG;
+    const int seg0 = blockIdx.x * G, seg = seg0 + g;
+    k0_stage<T, LG>(zs, qs, N, seg0, L);
+    if (seg >= nseg) return;
+    const int n = (int)min((int64_t)S0, N - (int64_t)seg * S0);
     const int ns = pp.mh + 1;
-    for (int l = 0; l < pp.mh; ++l) {
+    const double *z = L.z[g], *q = L.q[g];
+    if (l < pp.mh) {
+        // forward: referenced to the segment's last particle; backward: to its first
         const double br = pp.beta_re[l], bi = pp.beta_im[l];
         cx<double> fq{0, 0}, fz{0, 0}, bq{0, 0}, bz{0, 0}, e{1, 0};
-#pragma unroll
-        for (int j = 0; j < S0; ++j) {
-            if (j < n) {
-                const cx<double> d = j ? cexpm64(br, bi, z[j] - z[j - 1]) : cx<double>{1, 0};
-                fq = cmul(fq, d);
-                fz = cmul(fz, d);
-                fq.re += q[j];
-                fz.re += q[j] * z[j];
-                e = cmul(e, d);
-                bq.re += q[j] * e.re;
-                bq.im += q[j] * e.im;
-                bz.re += q[j] * z[j] * e.re;
-                bz.im += q[j] * z[j] * e.im;
-            }
+        for (int j = 0; j < n; ++j) {
+            const cx<double> d = j ? cexpm64(br, bi, z[j] - z[j - 1]) : cx<double>{1, 0};
+            const double qz = q[j] * z[j];
+            fq = cmul(fq, d);
+            fz = cmul(fz, d);
+            fq.re += q[j];
+            fz.re += qz;
+            e = cmul(e, d);
+            bq.re += q[j] * e.re;
+            bq.im += q[j] * e.im;
+            bz.re += qz * e.re;
+            bz.im += qz * e.im;
         }
         agg[a0_idx(nseg, ns, 0, seg, l, 0)] = fq;
         agg[a0_idx(nseg, ns, 0, seg, l, 1)] = fz;
         agg[a0_idx(nseg, ns, 1, seg, l, 0)] = bq;
         agg[a0_idx(nseg, ns, 1, seg, l, 1)] = bz;
     }
-    double sq = 0, sz = 0;
-#pragma unroll
-    for (int j = 0; j < S0; ++j) {
-        sq += q[j];
-        sz += q[j] * z[j];
+    if (l == 0) {
+        double sq = 0, sz = 0;
+        for (int j = 0; j < n; ++j) {
+            sq += q[j];
+            sz += q[j] * z[j];
+        }
+        agg[a0_idx(nseg, ns, 0, seg, pp.mh, 0)] = cx<double>{sq, 0};
+        agg[a0_idx(nseg, ns, 0, seg, pp.mh, 1)] = cx<double>{sz, 0};
+        agg[a0_idx(nseg, ns, 1, seg, pp.mh, 0)] = cx<double>{sq, 0};
+        agg[a0_idx(nseg, ns, 1, seg, pp.mh, 1)] = cx<double>{sz, 0};
     }
-    agg[a0_idx(nseg, ns, 0, seg, pp.mh, 0)] = cx<double>{sq, 0};
-    agg[a0_idx(nseg, ns, 0, seg, pp.mh, 1)] = cx<double>{sz, 0};
-    agg[a0_idx(nseg, ns, 1, seg, pp.mh, 0)] = cx<double>{sq, 0};
-    agg[a0_idx(nseg, ns, 1, seg, pp.mh, 1)] = cx<double>{sz, 0};
 }
 
-template <typename T>
-__global__ __launch_bounds__(128) void k0_sweep(const T *__restrict__ zs,
-                                                const T *__restrict__ qs, int64_t N, int nseg,
-                                                PairParams pp, double c_lin, double k0_self,
-                                                double two_pi_over_A,
-                                                const cx<double> *__restrict__ agg,
-                                                double *__restrict__ phi0,
-                                                double *__restrict__ fz0,
-                                                const double *__restrict__ rep_tpa,
-                                                const int32_t *__restrict__ seg_rep,
-                                                int seg_div) {
-    const int seg = blockIdx.x * blockDim.x + threadIdx.x;
-    if (seg >= nseg) return;
-    // replica batches: 2 pi / A of the replica holding this segment
-    if (rep_tpa) two_pi_over_A = rep_tpa[seg_rep[seg / seg_div]];
-    const int64_t i0 = (int64_t)seg * S0;
-    const int n = (int)min((int64_t)S0, N - i0);
-    double z[S0], q[S0], ph[S0], fz[S0];
-#pragma unroll
-    for (int j = 0; j < S0; ++j) {
-        z[j] = j < n ? (double)zs[i0 + j] : 0.0;
-        q[j] = j < n ? (double)qs[i0 + j] : 0.0;
-        ph[j] = 0.0;
-        fz[j] = 0.0;
-    }
+template <typename T, int LG>
+__global__ __launch_bounds__(WAVE) void k0_sweep(const T *__restrict__ zs,
+                                                 const T *__restrict__ qs, int64_t N, int nseg,
+                                                 PairParams pp, double c_lin, double k0_self,
+                                                 double two_pi_over_A,
+                                                 const cx<double> *__restrict__ agg,
+                                                 double *__restrict__ phi0,
+                                                 double *__restrict__ fz0,
+                                                 const double *__restrict__ rep_tpa,
+                                                 const int32_t *__restrict__ seg_rep,
+                                                 int seg_div) {
+    constexpr int G = K0Lds<LG>::G;
+    __shared__ K0Lds<LG> L;
+    const int g = threadIdx.x / LG, l = threadIdx.x % LG;
+    const int seg0 = blockIdx.x * G, seg = seg0 + g;
+    k0_stage<T, LG>(zs, qs, N, seg0, L);
+    const int n = seg < nseg ? (int)min((int64_t)S0, N - (int64_t)seg * S0) : 0;
     const int ns = pp.mh + 1;
-    for (int l = 0; l < pp.mh; ++l) {
-        const double br = pp.beta_re[l], bi = pp.beta_im[l];
-        const cx<double> cu{pp.c0u_re[l], pp.c0u_im[l]}, cv{pp.c0v_re[l], pp.c0v_im[l]};
-        const cx<double> fu{pp.f0u_re[l], pp.f0u_im[l]}, fv{pp.f0v_re[l], pp.f0v_im[l]};
-        // forward: U = sum_{j<i} q_j e^{..}, W = sum_{j<i} q_j z_j e^{..}, V = z_i U - W
-        cx<double> pq = agg[a0_idx(nseg, ns, 0, seg, l, 0)];
-        cx<double> pz = agg[a0_idx(nseg, ns, 0, seg, l, 1)];
+    const bool act = n > 0 && l < pp.mh;
+    const double *z = L.z[g], *q = L.q[g];
+    // pair l (zero coefficients on idle lanes); the linear terms count on lane 0 only
+    const int lc = act ? l : 0;
+    const double br = pp.beta_re[lc], bi = pp.beta_im[lc];
+    const double on = act ? 1.0 : 0.0;
+    const cx<double> cu{on * pp.c0u_re[lc], on * pp.c0u_im[lc]};
+    const cx<double> cv{on * pp.c0v_re[lc], on * pp.c0v_im[lc]};
+    const cx<double> fu{on * pp.f0u_re[lc], on * pp.f0u_im[lc]};
+    const cx<double> fv{on * pp.f0v_re[lc], on * pp.f0v_im[lc]};
+    const double lw = (l == 0 && n > 0) ? c_lin : 0.0;
+    const int sg = n > 0 ? seg : 0;
+    // forward: U = sum_{j<i} q_j e^{..}, W = sum_{j<i} q_j z_j e^{..}, V = z_i U - W;
+    // linear: Q, Z = sums of q and q z below
+    cx<double> pq{0, 0}, pz{0, 0};
+    if (act) {
+        pq = agg[a0_idx(nseg, ns, 0, sg, l, 0)];
+        pz = agg[a0_idx(nseg, ns, 0, sg, l, 1)];
+    }
+    double Q = n > 0 ? agg[a0_idx(nseg, ns, 0, sg, pp.mh, 0)].re : 0.0;
+    double Z = n > 0 ? agg[a0_idx(nseg, ns, 0, sg, pp.mh, 1)].re : 0.0;
+    for (int c0 = 0; c0 < S0; c0 += LG) {
+        double vp[LG], vf[LG];
 #pragma unroll
-        for (int j = 0; j < S0; ++j) {
+        for (int t = 0; t < LG; ++t) {
+            const int j = c0 + t;
+            vp[t] = vf[t] = 0.0;
             if (j < n) {
                 const cx<double> d = j ? cexpm64(br, bi, z[j] - z[j - 1]) : cx<double>{1, 0};
                 const cx<double> U = cmul(pq, d), W = cmul(pz, d);
                 const cx<double> V{z[j] * U.re - W.re, z[j] * U.im - W.im};
-                ph[j] += cu.re * U.re - cu.im * U.im + cv.re * V.re - cv.im * V.im;
-                fz[j] += fu.re * U.re - fu.im * U.im + fv.re * V.re - fv.im * V.im;
+                vp[t] = cu.re * U.re - cu.im * U.im + cv.re * V.re - cv.im * V.im +
+                        lw * (z[j] * Q - Z);
+                vf[t] = fu.re * U.re - fu.im * U.im + fv.re * V.re - fv.im * V.im + lw * Q;
                 pq = cx<double>{U.re + q[j], U.im};
                 pz = cx<double>{W.re + q[j] * z[j], W.im};
+                Q += q[j];
+                Z += q[j] * z[j];
             }
         }
-        // backward: U = sum_{j>i} q_j e^{..}, W = sum_{j>i} q_j z_j e^{..}, V = W - z_i U
-        pq = agg[a0_idx(nseg, ns, 1, seg, l, 0)];
-        pz = agg[a0_idx(nseg, ns, 1, seg, l, 1)];
+        const double sp = group_reduce_scatter<LG>(vp, l);
+        const double sf = group_reduce_scatter<LG>(vf, l);
+        L.ph[g][c0 + l] = sp;
+        L.fz[g][c0 + l] = sf;
+    }
+    // backward: U = sum_{j>i} q_j e^{..}, W = sum_{j>i} q_j z_j e^{..}, V = W - z_i U;
+    // linear: Q, Z = sums above
+    pq = pz = cx<double>{0, 0};
+    if (act) {
+        pq = agg[a0_idx(nseg, ns, 1, sg, l, 0)];
+        pz = agg[a0_idx(nseg, ns, 1, sg, l, 1)];
+    }
+    Q = n > 0 ? agg[a0_idx(nseg, ns, 1, sg, pp.mh, 0)].re : 0.0;
+    Z = n > 0 ? agg[a0_idx(nseg, ns, 1, sg, pp.mh, 1)].re : 0.0;
+    for (int c0 = S0 - LG; c0 >= 0; c0 -= LG) {
+        double vp[LG], vf[LG];
 #pragma unroll
-        for (int j = S0 - 1; j >= 0; --j) {
+        for (int t = LG - 1; t >= 0; --t) {
+            const int j = c0 + t;
+            vp[t] = vf[t] = 0.0;
             if (j < n) {
                 const cx<double> U = pq, W = pz;
                 const cx<double> V{W.re - z[j] * U.re, W.im - z[j] * U.im};
-                ph[j] += cu.re * U.re - cu.im * U.im + cv.re * V.re - cv.im * V.im;
-                fz[j] -= fu.re * U.re - fu.im * U.im + fv.re * V.re - fv.im * V.im;
+                vp[t] = cu.re * U.re - cu.im * U.im + cv.re * V.re - cv.im * V.im +
+                        lw * (Z - z[j] * Q);
+                vf[t] = -(fu.re * U.re - fu.im * U.im + fv.re * V.re - fv.im * V.im) - lw * Q;
+                Q += q[j];
+                Z += q[j] * z[j];
                 if (j) {
                     const cx<double> d = cexpm64(br, bi, z[j] - z[j - 1]);
                     pq = cmul(cx<double>{U.re + q[j], U.im}, d);
@@ -162,42 +237,50 @@ __global__ __launch_bounds__(128) void k0_sweep(const T *__restrict__ zs,
                 }
             }
         }
+        const double sp = group_reduce_scatter<LG>(vp, l);
+        const double sf = group_reduce_scatter<LG>(vf, l);
+        L.ph[g][c0 + l] += sp;
+        L.fz[g][c0 + l] += sf;
     }
-    // linear terms (beta = 0): prefix sums of q and q z below and above
-    double Qf = agg[a0_idx(nseg, ns, 0, seg, pp.mh, 0)].re;
-    double Zf = agg[a0_idx(nseg, ns, 0, seg, pp.mh, 1)].re;
-    double Qb = agg[a0_idx(nseg, ns, 1, seg, pp.mh, 0)].re;
-    double Zb = agg[a0_idx(nseg, ns, 1, seg, pp.mh, 1)].re;
-    double sq = 0, sz = 0;
-#pragma unroll
-    for (int j = 0; j < S0; ++j) {
-        sq += q[j];
-        sz += q[j] * z[j];
-    }
-    // Qb, Zb are the sums above the segment; add the segment's part above j
-    double aq = sq, az = sz;
-#pragma unroll
-    for (int j = 0; j < S0; ++j) {
-        if (j < n) {
-            aq -= q[j];
-            az -= q[j] * z[j];
-            const double qa = Qb + aq, za = Zb + az;
-            ph[j] += c_lin * ((z[j] * Qf - Zf) + (za - z[j] * qa));
-            fz[j] += c_lin * (Qf - qa);
-            Qf += q[j];
-            Zf += q[j] * z[j];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < S0; ++j) {
-        if (j < n) {
-            phi0[i0 + j] = -two_pi_over_A * (ph[j] + q[j] * k0_self);
-            fz0[i0 + j] = two_pi_over_A * fz[j];  // field: the target charge is applied later
+    __syncthreads();
+    for (int e = threadIdx.x; e < G * S0; e += WAVE) {
+        const int gg = e / S0, j = e % S0, s = seg0 + gg;
+        const int64_t i = (int64_t)s * S0 + j;
+        if (s < nseg && i < N) {
+            // replica batches: 2 pi / A of the replica holding this segment
+            const double tpa = rep_tpa ? rep_tpa[seg_rep[s / seg_div]] : two_pi_over_A;
+            phi0[i] = -tpa * (L.ph[gg][j] + L.q[gg][j] * k0_self);
+            fz0[i] = tpa * L.fz[gg][j];  // field: the target charge is applied later
         }
     }
 }
 
 }  // namespace
+
+// aggregates, carries and sweep with LG pair lanes per segment
+template <int LG>
+static q2d_status k0_launch(Plan *p, int64_t N, int nseg, const void *qsrc, double tpa,
+                            const double *rep_tpa, const int32_t *seg_rep, int seg_div) {
+    const int nb = (nseg + K0Lds<LG>::G - 1) / K0Lds<LG>::G;
+    cx<double> *agg = (cx<double> *)p->agg0.p;
+    if (p->fp32)
+        k0_agg<float, LG><<<nb, WAVE, 0, p->stream>>>((const float *)p->s_z.p,
+                                                       (const float *)qsrc, N, nseg, p->pp, agg);
+    else
+        k0_agg<double, LG><<<nb, WAVE, 0, p->stream>>>((const double *)p->s_z.p,
+                                                        (const double *)qsrc, N, nseg, p->pp, agg);
+    q2d_status st = carry_k0(p, nseg, S0, N);
+    if (st != Q2D_OK) return st;
+    if (p->fp32)
+        k0_sweep<float, LG><<<nb, WAVE, 0, p->stream>>>(
+            (const float *)p->s_z.p, (const float *)qsrc, N, nseg, p->pp, p->c_lin, p->k0_self,
+            tpa, agg, (double *)p->phi0.p, (double *)p->fz0.p, rep_tpa, seg_rep, seg_div);
+    else
+        k0_sweep<double, LG><<<nb, WAVE, 0, p->stream>>>(
+            (const double *)p->s_z.p, (const double *)qsrc, N, nseg, p->pp, p->c_lin, p->k0_self,
+            tpa, agg, (double *)p->phi0.p, (double *)p->fz0.p, rep_tpa, seg_rep, seg_div);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
 
 q2d_status k0_run(Plan *p, int64_t N) {
     if (N <= 0) return Q2D_OK;
@@ -212,31 +295,15 @@ q2d_status k0_run(Plan *p, int64_t N) {
     if ((st = ensure(p, p->phi0, (size_t)N * sizeof(double))) != Q2D_OK) return st;
     if ((st = ensure(p, p->fz0, (size_t)N * sizeof(double))) != Q2D_OK) return st;
     if ((st = spans_k0(p, nseg, S0, N)) != Q2D_OK) return st;
-    const int nb = (nseg + 127) / 128;
     const void *qsrc = p->src ? p->src : p->s_q.p;
     const double PI = 3.14159265358979323846;
     const double tpa = 2.0 * PI / (p->Lx * p->Ly);
     const double *rep_tpa = p->R ? (const double *)p->rep_tpa.p : nullptr;
     const int32_t *seg_rep = p->R ? (const int32_t *)p->seg_rep.p : nullptr;
     const int seg_div = p->R ? p->S_batch / S0 : 1;
-    if (p->fp32)
-        k0_agg<float><<<nb, 128, 0, p->stream>>>((const float *)p->s_z.p, (const float *)qsrc,
-                                                  N, nseg, p->pp, (cx<double> *)p->agg0.p);
-    else
-        k0_agg<double><<<nb, 128, 0, p->stream>>>((const double *)p->s_z.p,
-                                                   (const double *)qsrc, N, nseg, p->pp,
-                                                   (cx<double> *)p->agg0.p);
-    if ((st = carry_k0(p, nseg, S0, N)) != Q2D_OK) return st;
-    if (p->fp32)
-        k0_sweep<float><<<nb, 128, 0, p->stream>>>(
-            (const float *)p->s_z.p, (const float *)qsrc, N, nseg, p->pp, p->c_lin,
-            p->k0_self, tpa, (const cx<double> *)p->agg0.p, (double *)p->phi0.p,
-            (double *)p->fz0.p, rep_tpa, seg_rep, seg_div);
-    else
-        k0_sweep<double><<<nb, 128, 0, p->stream>>>(
-            (const double *)p->s_z.p, (const double *)qsrc, N, nseg, p->pp, p->c_lin,
-            p->k0_self, tpa, (const cx<double> *)p->agg0.p, (double *)p->phi0.p,
-            (double *)p->fz0.p, rep_tpa, seg_rep, seg_div);
+    st = mh <= 8 ? k0_launch<8>(p, N, nseg, qsrc, tpa, rep_tpa, seg_rep, seg_div)
+                 : k0_launch<16>(p, N, nseg, qsrc, tpa, rep_tpa, seg_rep, seg_div);
+    if (st != Q2D_OK) return st;
     tstop(p, 3);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }

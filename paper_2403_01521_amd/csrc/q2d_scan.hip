@@ -1056,7 +1056,9 @@ q2d_status carry_run(Plan *p, const CArgs<T> &ca, Buf &tmp) {
     const int64_t nt = (int64_t)ca.ncols * nr;
     const int nb = (int)((nt + 255) / 256);
     k_cfold<T, KMODE><<<nb, 256, 0, p->stream>>>(ca, nr, rc);
-    if (nr > 1024)
+    // (1024-thread work-groups wait for a nearly idle CU while other passes
+    // run concurrently: only for very long columns)
+    if (nr > 4096)
         k_cscan<1024><<<ca.ncols, 1024, 0, p->stream>>>(ca.ncols, nr, rc);
     else
         k_cscan<256><<<ca.ncols, 256, 0, p->stream>>>(ca.ncols, nr, rc);
@@ -1179,11 +1181,6 @@ void launch_agg(Plan *p, const KArgs<T> &ka, int blocks) {
         }
     }
     dispatch_agg<T>(p, ka, dim3(blocks));
-}
-
-int env_int(const char *name, int dflt) {
-    const char *v = getenv(name);
-    return (v && *v) ? atoi(v) : dflt;
 }
 
 // segment length: multiple of 64, at most SMAX, aiming at ~2048 segments
