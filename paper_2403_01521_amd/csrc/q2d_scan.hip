@@ -75,22 +75,27 @@ __device__ inline cx<float> cexpm(float br, float bi, float t) {
     }
     return {m * c, -m * s};
 }
+// sum_{k <= ND} (-x)^k / k! by Horner in -x (x = ar + i ai)
+template <int ND>
+__device__ inline cx<double> expm_taylor(double ar, double ai) {
+    constexpr double inv_fact[8] = {1.0,         1.0,         1.0 / 2,     1.0 / 6,
+                                    1.0 / 24,    1.0 / 120,   1.0 / 720,   1.0 / 5040};
+    double pr = inv_fact[ND], pi = 0.0;
+#pragma unroll
+    for (int k = ND - 1; k >= 0; --k) {
+        const double nr = -(pr * ar - pi * ai), ni = -(pr * ai + pi * ar);
+        pr = nr + inv_fact[k];
+        pi = ni;
+    }
+    return {pr, pi};
+}
+// small arguments r = |ar| + |ai|: Taylor polynomials with remainder
+// r^{n+1}/(n+1)! < 1e-17 (degree 4 below 2^-10, degree 7 below 2^-6)
 __device__ inline cx<double> cexpm(double br, double bi, double t) {
     const double ar = br * t, ai = bi * t;
-    if (fabs(ar) + fabs(ai) < 0.015625) {
-        // e^{-x}, |x| < 2^-6: Taylor to x^7 (remainder < 1e-19)
-        const double xr = ar, xi = ai;
-        double pr = 1.0 / 5040.0, pi = 0.0;
-        const double cs[7] = {1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0, 0.5, 1.0, 1.0};
-        // p(x) = sum_n (-x)^n / n!: Horner in (-x)
-#pragma unroll
-        for (int n = 0; n < 7; ++n) {
-            const double nr = -(pr * xr - pi * xi), ni = -(pr * xi + pi * xr);
-            pr = nr + cs[n];
-            pi = ni;
-        }
-        return {pr, pi};
-    }
+    const double r = fabs(ar) + fabs(ai);
+    if (r < 0x1p-10) return expm_taylor<4>(ar, ai);
+    if (r < 0x1p-6) return expm_taylor<7>(ar, ai);
     const double m = exp(-ar);
     double s, c;
     sincos(ai, &s, &c);
