@@ -256,10 +256,12 @@ q2d_status k0_side(Plan *p, int64_t N) {
     if (hipEventRecord(p->ev_sorted, p->stream) != hipSuccess ||
         hipStreamWaitEvent(p->side, p->ev_sorted, 0) != hipSuccess)
         return Q2D_EDEVICE;
-    q2d_status st;
+    q2d_status st = Q2D_OK;
     {
         SideScope side(p);
-        st = k0_run(p, N);
+        // the epilogue's inverse permutation, off the critical path
+        if (!p->R && (st = launch_inv(p, N)) == Q2D_OK) p->inv_ready = true;
+        if (st == Q2D_OK) st = k0_run(p, N);
     }
     if (st != Q2D_OK) return st;
     return hipEventRecord(p->ev_k0, p->side) == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
@@ -454,7 +456,7 @@ void plan_release(Plan *p) {
                    &p->user_modes, &p->user_w, &p->user_coef, &p->s_g, &p->fq,
                    &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
                    &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->carry_tmp, &p->outk, &p->spans0,
-                   &p->agg0, &p->carry_tmp0, &p->phi0, &p->fz0, &p->epart, &p->status,
+                   &p->agg0, &p->carry_tmp0, &p->phi0, &p->fz0, &p->epart, &p->inv, &p->status,
                    &p->cell_start, &p->cell_count, &p->cell_idx, &p->cell_tmp, &p->rep_box,
                    &p->rep_H, &p->rep_diag, &p->rep_tpa, &p->rep_of, &p->rep_off, &p->rep_poff,
                    &p->seg_rep, &p->pperm, &p->epart_rep, &p->step_ctr};

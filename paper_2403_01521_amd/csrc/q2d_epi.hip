@@ -17,15 +17,16 @@ namespace {
 
 constexpr int EPI_THREADS = 256;
 
+// Combine in sorted order.  The result {phi, F_x, F_y, F_z} of particle i
+// replaces chunk 0's entry i (each thread reads its own entries first), and
+// k_unsort moves it to input order: random 16-byte reads instead of the
+// partial-line writes of a scatter.
 template <typename T>
-__global__ __launch_bounds__(EPI_THREADS) void k_epi(int64_t N, int nchunks,
-                                                     const T *__restrict__ outk,
+__global__ __launch_bounds__(EPI_THREADS) void k_epi(int64_t N, int nchunks, T *__restrict__ outk,
                                                      const T *__restrict__ qs,
                                                      const double *__restrict__ phi0,
-                                                     const double *__restrict__ fz0,
-                                                     const int32_t *__restrict__ perm, double diag,
-                                                     double self_c, T *__restrict__ phi,
-                                                     T *__restrict__ F, double *__restrict__ epart) {
+                                                     const double *__restrict__ fz0, double diag,
+                                                     double self_c, double *__restrict__ epart) {
     __shared__ double red[EPI_THREADS];
     const int64_t i = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
     double e = 0.0;
@@ -40,13 +41,11 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epi(int64_t N, int nchunks,
         }
         const double q = (double)qs[i];
         const double ph = o0 + q * diag + (phi0 ? phi0[i] : 0.0) - self_c * q;
-        const int64_t orig = perm[i];
-        if (phi) phi[orig] = (T)ph;
-        if (F) {
-            F[3 * orig] = (T)(q * o1);
-            F[3 * orig + 1] = (T)(q * o2);
-            F[3 * orig + 2] = (T)(q * (o3 + (fz0 ? fz0[i] : 0.0)));
-        }
+        T *r = outk + i * 4;
+        r[0] = (T)ph;
+        r[1] = (T)(q * o1);
+        r[2] = (T)(q * o2);
+        r[3] = (T)(q * (o3 + (fz0 ? fz0[i] : 0.0)));
         e = q * ph;
     }
     red[threadIdx.x] = e;
@@ -56,6 +55,28 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epi(int64_t N, int nchunks,
         __syncthreads();
     }
     if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
+}
+
+// input order: particle o takes the combined result of its sorted slot inv[o]
+template <typename T>
+__global__ __launch_bounds__(EPI_THREADS) void k_unsort(int64_t N, const T *__restrict__ res,
+                                                        const int32_t *__restrict__ inv,
+                                                        T *__restrict__ phi, T *__restrict__ F) {
+    const int64_t o = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
+    if (o >= N) return;
+    const T *r = res + (int64_t)inv[o] * 4;
+    if (phi) phi[o] = r[0];
+    if (F) {
+        F[3 * o] = r[1];
+        F[3 * o + 1] = r[2];
+        F[3 * o + 2] = r[3];
+    }
+}
+
+__global__ __launch_bounds__(EPI_THREADS) void k_inv(const int32_t *__restrict__ perm, int64_t N,
+                                                     int32_t *__restrict__ inv) {
+    const int64_t i = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
+    if (i < N) inv[perm[i]] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(EPI_THREADS) void k_energy(const double *__restrict__ epart,
@@ -147,17 +168,42 @@ q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0,
     const double self_c = with_k0 ? 2.0 * p->alpha / sqrt(3.14159265358979323846) : 0.0;
     const double *phi0 = with_k0 ? (const double *)p->phi0.p : nullptr;
     const double *fz0 = with_k0 ? (const double *)p->fz0.p : nullptr;
+    const bool out = phi || F;
+    const bool need_inv = out && !p->inv_ready;
+    // k_epi writes each particle's result over chunk 0 of outk: with no chunks
+    // (no modes) the buffer may not exist yet; with chunks it already holds
+    // n_chunks x N x 4 values and ensure() keeps it
+    const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+    if ((st = ensure(p, p->outk, (size_t)N * 4 * tsz)) != Q2D_OK) return st;
+    p->inv_ready = false;
+    if (need_inv && (st = launch_inv(p, N)) != Q2D_OK) return st;
     if (p->fp32)
-        k_epi<float><<<nb, EPI_THREADS, 0, p->stream>>>(
-            N, n_chunks, (const float *)p->outk.p, (const float *)p->s_q.p, phi0, fz0, p->perm,
-            diag, self_c,
-            (float *)phi, (float *)F, (double *)p->epart.p);
+        k_epi<float><<<nb, EPI_THREADS, 0, p->stream>>>(N, n_chunks, (float *)p->outk.p,
+                                                        (const float *)p->s_q.p, phi0, fz0, diag,
+                                                        self_c, (double *)p->epart.p);
     else
-        k_epi<double><<<nb, EPI_THREADS, 0, p->stream>>>(
-            N, n_chunks, (const double *)p->outk.p, (const double *)p->s_q.p, phi0, fz0, p->perm,
-            diag, self_c,
-            (double *)phi, (double *)F, (double *)p->epart.p);
+        k_epi<double><<<nb, EPI_THREADS, 0, p->stream>>>(N, n_chunks, (double *)p->outk.p,
+                                                         (const double *)p->s_q.p, phi0, fz0,
+                                                         diag, self_c, (double *)p->epart.p);
+    if (out) {
+        const int32_t *inv = (const int32_t *)p->inv.p;
+        if (p->fp32)
+            k_unsort<float><<<nb, EPI_THREADS, 0, p->stream>>>(N, (const float *)p->outk.p, inv,
+                                                               (float *)phi, (float *)F);
+        else
+            k_unsort<double><<<nb, EPI_THREADS, 0, p->stream>>>(N, (const double *)p->outk.p, inv,
+                                                                (double *)phi, (double *)F);
+    }
     if (E) k_energy<<<1, EPI_THREADS, 0, p->stream>>>((const double *)p->epart.p, nb, E);
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+q2d_status launch_inv(Plan *p, int64_t N) {
+    if (N <= 0) return Q2D_OK;
+    q2d_status st = ensure(p, p->inv, (size_t)N * sizeof(int32_t));
+    if (st != Q2D_OK) return st;
+    k_inv<<<(int)((N + EPI_THREADS - 1) / EPI_THREADS), EPI_THREADS, 0, p->stream>>>(
+        p->perm, N, (int32_t *)p->inv.p);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 

@@ -111,6 +111,8 @@ struct Plan {
 
     // epilogue and status
     Buf epart;
+    Buf inv;                   // int32 inverse of perm (input index -> sorted index)
+    bool inv_ready = false;    // inv already enqueued for the current call (side stream)
     Buf status;                // int32 device status word
 
     // short range
@@ -201,6 +203,8 @@ q2d_status kmodes_run(Plan *p, int64_t N, const int32_t *modes, const void *coef
 q2d_status k0_run(Plan *p, int64_t N);
 
 // combine, unsort, energy
+// inverse permutation of the current sort, on p->stream (single systems)
+q2d_status launch_inv(Plan *p, int64_t N);
 q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0, void *phi,
                     void *F, double *E);
 

@@ -150,11 +150,21 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t tile0 = (int64_t)blockIdx.x * SORT_TILE;
+    // the tile's keys and values, loaded up front (one memory latency, not one per round)
+    K ks[SORT_ITEMS];
+    int32_t vs[SORT_ITEMS];
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int64_t i = tile0 + r * SORT_THREADS + t;
+        ks[r] = i < N ? kin[i] : (K)0;
+        vs[r] = i < N ? vin[i] : 0;
+    }
+#pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const int64_t i = tile0 + r * SORT_THREADS + t;
         const bool valid = i < N;
-        const K k = valid ? kin[i] : (K)0;
-        const int32_t v = valid ? vin[i] : 0;
+        const K k = ks[r];
+        const int32_t v = vs[r];
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -438,6 +448,7 @@ q2d_status sort_batch_impl(Plan *p, const void *pos_v, const void *q_v) {
 }  // namespace
 
 q2d_status sort_and_stage_batch(Plan *p, const void *pos, const void *q) {
+    p->inv_ready = false;
     tstart(p, 2);
     q2d_status st = p->fp32 ? sort_batch_impl<float, uint32_t>(p, pos, q)
                             : sort_batch_impl<double, uint64_t>(p, pos, q);
@@ -460,6 +471,7 @@ q2d_status gather_sources(Plan *p, const void *g, int64_t N) {
 }
 
 q2d_status sort_and_stage(Plan *p, const void *pos, const void *q, int64_t N) {
+    p->inv_ready = false;  // a new order: any earlier inverse permutation is stale
     tstart(p, 2);
     q2d_status st = p->fp32 ? sort_impl<float, uint32_t>(p, pos, q, N)
                             : sort_impl<double, uint64_t>(p, pos, q, N);
