@@ -67,61 +67,83 @@ __device__ inline int64_t a0_idx(int nseg, int ns, int dir, int seg, int slot, i
     return (((int64_t)dir * nseg + seg) * ns + slot) * 2 + inp;
 }
 
-template <int LG>
+template <typename T, int LG>
 struct K0Lds {
     static constexpr int G = WAVE / LG;  // segments per wave
-    double z[G][ZP], q[G][ZP];
+    T z[G][ZP], q[G][ZP];                // inputs in their own precision
     double ph[G][ZP], fz[G][ZP];
+    double rb[G][LG][LG + 1];            // per-group reduction rows [step][pair lane]
+    // pair coefficients: beta (re, im), then c0u, c0v, f0u, f0v (re, im) per pair
+    double cf[10][MAX_PAIRS];
 };
+
+// the pair tables, copied with uniform indices (a lane-dependent index into
+// the kernel-argument struct would compile to select chains over all entries)
+template <typename T, int LG>
+__device__ inline void k0_coefs(const PairParams &pp, K0Lds<T, LG> &L) {
+    if (threadIdx.x == 0) {
+        for (int l = 0; l < pp.mh; ++l) {
+            L.cf[0][l] = pp.beta_re[l];
+            L.cf[1][l] = pp.beta_im[l];
+            L.cf[2][l] = pp.c0u_re[l];
+            L.cf[3][l] = pp.c0u_im[l];
+            L.cf[4][l] = pp.c0v_re[l];
+            L.cf[5][l] = pp.c0v_im[l];
+            L.cf[6][l] = pp.f0u_re[l];
+            L.cf[7][l] = pp.f0u_im[l];
+            L.cf[8][l] = pp.f0v_re[l];
+            L.cf[9][l] = pp.f0v_im[l];
+        }
+    }
+}
 
 // heights and sources of the wave's segments (zero past N)
 template <typename T, int LG>
 __device__ inline void k0_stage(const T *__restrict__ zs, const T *__restrict__ qs, int64_t N,
-                                int seg0, K0Lds<LG> &L) {
-    constexpr int G = K0Lds<LG>::G;
+                                int seg0, K0Lds<T, LG> &L) {
+    constexpr int G = K0Lds<T, LG>::G;
     for (int e = threadIdx.x; e < G * S0; e += WAVE) {
         const int g = e / S0, j = e % S0;
         const int64_t i = (int64_t)(seg0 + g) * S0 + j;
-        L.z[g][j] = i < N ? (double)zs[i] : 0.0;
-        L.q[g][j] = i < N ? (double)qs[i] : 0.0;
+        L.z[g][j] = i < N ? zs[i] : (T)0;
+        L.q[g][j] = i < N ? qs[i] : (T)0;
     }
     __syncthreads();
 }
 
-// Sum v[t] over the LG lanes of a group; lane l of the group gets the sum for
-// t = l.  Level h: lanes with bit h set keep the upper half of what is left
-// and pass the lower half to their partner l ^ h.
+// Sum v[t] over the LG pair lanes of a group; lane l of the group gets the sum
+// for t = l.  Through LDS rows (a register butterfly with lane-dependent
+// selects is turned by the compiler into dynamic indexing); the pair lanes are
+// added in a fixed order.  The work-group is one wave.
 template <int LG>
-__device__ inline double group_reduce_scatter(double (&v)[LG], int l) {
+__device__ inline double group_sum(const double (&v)[LG], double (*rb)[LG + 1], int l) {
 #pragma unroll
-    for (int h = LG / 2; h >= 1; h >>= 1) {
-        const bool hi = (l & h) != 0;
+    for (int t = 0; t < LG; ++t) rb[t][l] = v[t];
+    __syncthreads();
+    double s = 0.0;
 #pragma unroll
-        for (int t = 0; t < h; ++t) {
-            const double keep = hi ? v[t + h] : v[t];
-            const double send = hi ? v[t] : v[t + h];
-            v[t] = keep + __shfl_xor(send, h);
-        }
-    }
-    return v[0];
+    for (int u = 0; u < LG; ++u) s += rb[l][u];
+    __syncthreads();
+    return s;
 }
 
 template <typename T, int LG>
 __global__ __launch_bounds__(WAVE) void k0_agg(const T *__restrict__ zs, const T *__restrict__ qs,
                                                int64_t N, int nseg, PairParams pp,
                                                cx<double> *__restrict__ agg) {
-    constexpr int G = K0Lds<LG>::G;
-    __shared__ K0Lds<LG> L;
+    constexpr int G = K0Lds<T, LG>::G;
+    __shared__ K0Lds<T, LG> L;
     const int g = threadIdx.x / LG, l = threadIdx.x % LG;
     const int seg0 = blockIdx.x * G, seg = seg0 + g;
+    k0_coefs<T, LG>(pp, L);
     k0_stage<T, LG>(zs, qs, N, seg0, L);
     if (seg >= nseg) return;
     const int n = (int)min((int64_t)S0, N - (int64_t)seg * S0);
     const int ns = pp.mh + 1;
-    const double *z = L.z[g], *q = L.q[g];
+    const T *z = L.z[g], *q = L.q[g];
     if (l < pp.mh) {
         // forward: referenced to the segment's last particle; backward: to its first
-        const double br = pp.beta_re[l], bi = pp.beta_im[l];
+        const double br = L.cf[0][l], bi = L.cf[1][l];
         cx<double> fq{0, 0}, fz{0, 0}, bq{0, 0}, bz{0, 0}, e{1, 0};
         for (int j = 0; j < n; ++j) {
             const cx<double> d = j ? cexpm64(br, bi, z[j] - z[j - 1]) : cx<double>{1, 0};
@@ -165,23 +187,24 @@ __global__ __launch_bounds__(WAVE) void k0_sweep(const T *__restrict__ zs,
                                                  const double *__restrict__ rep_tpa,
                                                  const int32_t *__restrict__ seg_rep,
                                                  int seg_div) {
-    constexpr int G = K0Lds<LG>::G;
-    __shared__ K0Lds<LG> L;
+    constexpr int G = K0Lds<T, LG>::G;
+    __shared__ K0Lds<T, LG> L;
     const int g = threadIdx.x / LG, l = threadIdx.x % LG;
     const int seg0 = blockIdx.x * G, seg = seg0 + g;
+    k0_coefs<T, LG>(pp, L);
     k0_stage<T, LG>(zs, qs, N, seg0, L);
     const int n = seg < nseg ? (int)min((int64_t)S0, N - (int64_t)seg * S0) : 0;
     const int ns = pp.mh + 1;
     const bool act = n > 0 && l < pp.mh;
-    const double *z = L.z[g], *q = L.q[g];
+    const T *z = L.z[g], *q = L.q[g];
     // pair l (zero coefficients on idle lanes); the linear terms count on lane 0 only
     const int lc = act ? l : 0;
-    const double br = pp.beta_re[lc], bi = pp.beta_im[lc];
+    const double br = L.cf[0][lc], bi = L.cf[1][lc];
     const double on = act ? 1.0 : 0.0;
-    const cx<double> cu{on * pp.c0u_re[lc], on * pp.c0u_im[lc]};
-    const cx<double> cv{on * pp.c0v_re[lc], on * pp.c0v_im[lc]};
-    const cx<double> fu{on * pp.f0u_re[lc], on * pp.f0u_im[lc]};
-    const cx<double> fv{on * pp.f0v_re[lc], on * pp.f0v_im[lc]};
+    const cx<double> cu{on * L.cf[2][lc], on * L.cf[3][lc]};
+    const cx<double> cv{on * L.cf[4][lc], on * L.cf[5][lc]};
+    const cx<double> fu{on * L.cf[6][lc], on * L.cf[7][lc]};
+    const cx<double> fv{on * L.cf[8][lc], on * L.cf[9][lc]};
     const double lw = (l == 0 && n > 0) ? c_lin : 0.0;
     const int sg = n > 0 ? seg : 0;
     // forward: U = sum_{j<i} q_j e^{..}, W = sum_{j<i} q_j z_j e^{..}, V = z_i U - W;
@@ -212,8 +235,8 @@ __global__ __launch_bounds__(WAVE) void k0_sweep(const T *__restrict__ zs,
                 Z += q[j] * z[j];
             }
         }
-        const double sp = group_reduce_scatter<LG>(vp, l);
-        const double sf = group_reduce_scatter<LG>(vf, l);
+        const double sp = group_sum<LG>(vp, L.rb[g], l);
+        const double sf = group_sum<LG>(vf, L.rb[g], l);
         L.ph[g][c0 + l] = sp;
         L.fz[g][c0 + l] = sf;
     }
@@ -247,8 +270,8 @@ __global__ __launch_bounds__(WAVE) void k0_sweep(const T *__restrict__ zs,
                 }
             }
         }
-        const double sp = group_reduce_scatter<LG>(vp, l);
-        const double sf = group_reduce_scatter<LG>(vf, l);
+        const double sp = group_sum<LG>(vp, L.rb[g], l);
+        const double sf = group_sum<LG>(vf, L.rb[g], l);
         L.ph[g][c0 + l] += sp;
         L.fz[g][c0 + l] += sf;
     }
@@ -259,7 +282,7 @@ __global__ __launch_bounds__(WAVE) void k0_sweep(const T *__restrict__ zs,
         if (s < nseg && i < N) {
             // replica batches: 2 pi / A of the replica holding this segment
             const double tpa = rep_tpa ? rep_tpa[seg_rep[s / seg_div]] : two_pi_over_A;
-            phi0[i] = -tpa * (L.ph[gg][j] + L.q[gg][j] * k0_self);
+            phi0[i] = -tpa * (L.ph[gg][j] + (double)L.q[gg][j] * k0_self);
             fz0[i] = tpa * L.fz[gg][j];  // field: the target charge is applied later
         }
     }
@@ -271,7 +294,7 @@ __global__ __launch_bounds__(WAVE) void k0_sweep(const T *__restrict__ zs,
 template <int LG>
 static q2d_status k0_launch(Plan *p, int64_t N, int nseg, const void *qsrc, double tpa,
                             const double *rep_tpa, const int32_t *seg_rep, int seg_div) {
-    const int nb = (nseg + K0Lds<LG>::G - 1) / K0Lds<LG>::G;
+    const int nb = (nseg + K0Lds<float, LG>::G - 1) / K0Lds<float, LG>::G;
     cx<double> *agg = (cx<double> *)p->agg0.p;
     if (p->fp32)
         k0_agg<float, LG><<<nb, WAVE, 0, p->stream>>>((const float *)p->s_z.p,

@@ -300,309 +300,226 @@ __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// pass 1 on the matrix cores (FP32, units of >= 32 modes per segment group).
-// Per segment the aggregates are one dense contraction over its particles j,
-//   C[(source, mode)][(dir, slot, re/im)] = sum_j src_j(mode) E_dir,slot(j),
-// src = q cos / q sin of the mode's phase (computed per (mode, particle) on
-// the VALU) and E the mode-independent decays to the segment's ends (LDS).
-// v_mfma_f32_16x16x4f32 takes 4 particles per step: lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 (l / 16) + v][l % 16]
-// in accumulator register v.  A wave's 128 rows (2 sources x 64 modes, over
-// its F segments) form 8 row tiles; the 4 MH columns form NCT column tiles.
-// The beta = k term (mode-dependent decay) stays on the VALU: each lane sums
-// its quarter of the particles and the four quarters are added at the end.
+// pass 1 on the fp16 matrix cores with split operands (FP32 plans, M <= 24).
+// Every FP32 operand v is carried as v_hi + v_lo with v_hi = fp16(v) and
+// v_lo = fp16(v - v_hi); the products hi*hi + hi*lo + lo*hi, accumulated in
+// FP32, leave an error of about 2^-21 |v| |w| per term (the lo*lo term and the
+// two roundings), the size of FP32 rounding over a segment's sum.  The decays
+// satisfy |E| <= 1; the sources are scaled by a power of two that brings the
+// segment's largest |q| below 1 (undone exactly on the result), so no fp16
+// overflow can occur.  v_mfma_f32_16x16x32_f16 takes 32 particles per
+// instruction: lane l supplies A[l % 16][8 (l / 16) + e] and
+// B[8 (l / 16) + e][l % 16] (e < 8) and holds D[4 (l / 16) + v][l % 16].
 // ---------------------------------------------------------------------------
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 template <int MH>
-struct AggLds {
+struct alignas(16) AggLdsH {
+    static constexpr int NCP = (4 * MH + 15) / 16 * 16;  // columns padded to whole tiles
+    static constexpr int RP = WAVE + 8;                   // row pitch in halves (16-byte rows)
     uint32_t ux[WAVE], uy[WAVE];
     float q[WAVE], zf[WAVE], zb[WAVE];
-    float e[(4 * MH + 15) / 16 * 16][WAVE + 1];  // decays [column][entry]
+    _Float16 eh[NCP][RP], el[NCP][RP];                    // decays [column][entry], hi and lo
 };
 
-template <int MH, int F>
-__device__ inline void agg_mfma_body(const KArgs<float> &a, const LaneMap &lm, AggLds<MH> &L) {
-    constexpr int NC = 4 * MH;            // columns: (dir, slot, re/im)
-    constexpr int NCT = (NC + 15) / 16;   // column tiles
-    constexpr int WB = WAVE / F, BS = WB; // modes per segment group, steps per block
-    constexpr int TPS = 2 * WB / 16;      // row tiles per segment
-    constexpr int HT = TPS / 2;           // row tiles per source per segment
-    const int lane = threadIdx.x;
-    uint32_t *c_ux = L.ux, *c_uy = L.uy;
-    float *c_q = L.q, *c_zf = L.zf, *c_zb = L.zb;
-    auto &c_e = L.e;
-    for (int c = NC; c < NCT * 16; ++c) c_e[c][lane] = 0.f;
-    // load role: lane loads step js of segment lm.f into entry js * F + lm.f
-    const int js = lane % BS, wi = js * F + lm.f;
-    const float s_zf = lm.n > 0 ? a.z[lm.i0] : 0.f, s_zl = lm.n > 0 ? a.z[lm.i0 + lm.n - 1] : 0.f;
-    const int nblk = a.S / BS;
-    // compute role: lane = 16 kq + i; pair p = (segment p / HT, mode 16 (p % HT) + i)
-    const int i = lane & 15, kq = lane >> 4;
-    const int ng = (lm.u.nm + WB - 1) / WB;
-    for (int g = 0; g < ng; ++g) {
-        int pmx[4], pmy[4];
-        float pk[4];
+__device__ inline void split8(const float (&v)[8], h8v &hi, h8v &lo) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int seg = lm.wave * F + p / HT;
-            const int rep = (a.seg_rep && seg < a.nseg) ? a.seg_rep[seg] : 0;
-            const int ml = g * WB + 16 * (p % HT) + i;
-            const bool mv = ml < lm.u.nm;
-            const int m = lm.u.m0 + ml;
-            const int64_t mb = (int64_t)rep * a.rep_mstride, cb = (int64_t)rep * a.rep_cstride;
-            pmx[p] = mv ? a.modes[mb + a.moff + m] : 0;
-            pmy[p] = mv ? a.modes[mb + a.mstride + a.moff + m] : 0;
-            pk[p] = mv ? a.coef[cb + 2 * a.cstride + a.moff + m] : 0.f;
-        }
-        f4v acc[8][NCT];
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-#pragma unroll
-            for (int c = 0; c < NCT; ++c) acc[t][c] = f4v{0.f, 0.f, 0.f, 0.f};
-        float fk[4][4];  // per pair: fwd x, fwd y, bwd x, bwd y of the beta = k term
-#pragma unroll
-        for (int p = 0; p < 4; ++p) fk[p][0] = fk[p][1] = fk[p][2] = fk[p][3] = 0.f;
-        for (int blk = 0; blk < nblk; ++blk) {
-            __syncthreads();
-            {
-                const int pos = blk * BS + js;
-                uint32_t ux = 0, uy = 0;
-                float qv = 0.f, tf = 0.f, tb = 0.f;
-                if (pos < lm.n) {
-                    const int64_t pp = lm.i0 + pos;
-                    ux = a.ux[pp];
-                    uy = a.uy[pp];
-                    qv = a.q[pp];
-                    const float zp = a.z[pp];
-                    tf = s_zl - zp;
-                    tb = zp - s_zf;
-                }
-                c_ux[wi] = ux;
-                c_uy[wi] = uy;
-                c_q[wi] = qv;
-                c_zf[wi] = tf;
-                c_zb[wi] = tb;
-#pragma unroll
-                for (int l = 0; l < MH; ++l) {
-                    const cx<float> ef = cexpm(a.bre[l], a.bim[l], tf);
-                    const cx<float> eb = cexpm(a.bre[l], a.bim[l], tb);
-                    c_e[2 * l][wi] = ef.re;
-                    c_e[2 * l + 1][wi] = ef.im;
-                    c_e[2 * MH + 2 * l][wi] = eb.re;
-                    c_e[2 * MH + 2 * l + 1][wi] = eb.im;
-                }
-            }
-            __syncthreads();
-#pragma unroll 1
-            for (int kk = 0; kk < BS / 4; ++kk) {
-                const int jj = 4 * kk + kq;  // this lane's particle (step) in the block
-                float xs[4], ys[4];
-#pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    const int e = jj * F + p / HT;
-                    float sn, cs;
-                    phase_sc(pmx[p], pmy[p], c_ux[e], c_uy[e], sn, cs);
-                    const float qv = c_q[e];
-                    xs[p] = qv * cs;
-                    ys[p] = qv * sn;
-                    const float ef = __expf(-pk[p] * c_zf[e]), eb = __expf(-pk[p] * c_zb[e]);
-                    fk[p][0] = fma(xs[p], ef, fk[p][0]);
-                    fk[p][1] = fma(ys[p], ef, fk[p][1]);
-                    fk[p][2] = fma(xs[p], eb, fk[p][2]);
-                    fk[p][3] = fma(ys[p], eb, fk[p][3]);
-                }
-#pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    const int e = jj * F + f;
-                    float bv[NCT];
-#pragma unroll
-                    for (int c = 0; c < NCT; ++c) bv[c] = c_e[16 * c + i][e];
-#pragma unroll
-                    for (int u = 0; u < TPS; ++u) {
-                        const int t = f * TPS + u;
-                        const int p = f * HT + u % HT;
-                        const float av = (u < HT) ? xs[p] : ys[p];
-#pragma unroll
-                        for (int c = 0; c < NCT; ++c)
-                            acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[c], acc[t][c],
-                                                                              0, 0, 0);
-                    }
-                }
-            }
-        }
-        // aggregates: tile t, column tile c, register v -> row 4 kq + v of the
-        // tile, column 16 c + i
-        float *aggf = (float *)a.agg;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int f = t / TPS, u = t % TPS;
-            const int inp = u / HT, mc = u % HT;
-            const int seg = lm.wave * F + f;
-            if (seg >= a.nseg) continue;
-#pragma unroll
-            for (int c = 0; c < NCT; ++c) {
-                const int col = 16 * c + i;
-                if (col >= NC) continue;
-                const int dir = col / (2 * MH), slot = (col % (2 * MH)) / 2, ri = col % 2;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int m = lm.u.m0 + g * WB + 16 * mc + 4 * kq + v;
-                    if (m < a.gpad)
-                        aggf[2 * agg_idx<MH>(a.nseg, a.gpad, dir, seg, slot, inp, m) + ri] =
-                            acc[t][c][v];
-                }
-            }
-        }
-        // beta = k term: add the four particle quarters (lanes i, i+16, i+32, i+48)
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                float v = fk[p][w];
-                v += __shfl_xor(v, 16);
-                v += __shfl_xor(v, 32);
-                fk[p][w] = v;
-            }
-        if (kq == 0) {
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int seg = lm.wave * F + p / HT;
-                const int m = lm.u.m0 + g * WB + 16 * (p % HT) + i;
-                if (seg < a.nseg && m < a.gpad) {
-                    a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 0, m)] = cx<float>{fk[p][0], 0.f};
-                    a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 1, m)] = cx<float>{fk[p][1], 0.f};
-                    a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 0, m)] = cx<float>{fk[p][2], 0.f};
-                    a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 1, m)] = cx<float>{fk[p][3], 0.f};
-                }
-            }
-        }
+    for (int e = 0; e < 8; ++e) {
+        const _Float16 h = (_Float16)v[e];
+        hi[e] = h;
+        lo[e] = (_Float16)(v[e] - (float)h);
     }
 }
 
-template <int MH>
-__global__ __launch_bounds__(64) void k_agg_mfma(const KArgs<float> a) {
-    __shared__ AggLds<MH> L;
-    const LaneMap lm = lane_map(a);
-    // units here have F in {1, 2} (uniform per work-group)
-    if (lm.u.F == 1)
-        agg_mfma_body<MH, 1>(a, lm, L);
-    else
-        agg_mfma_body<MH, 2>(a, lm, L);
-}
+// One work-group per segment computes the aggregates of every mode of the
+// launch (independent of the sweep's mode units): the decays of a block of 64
+// particles are staged in LDS once for all its waves, and each wave takes CPW
+// chunks of 16 modes (rows: the x and y sources of each chunk).  The
+// beta = k term (mode-dependent decay) stays on the VALU.
+constexpr int AGW_MAX = 8;  // waves per work-group at most
+constexpr int AGG_CPW = 2;  // 16-mode chunks per wave (measured best of 1, 2, 4)
 
-// ---------------------------------------------------------------------------
-// pass 1 for narrow bands (wb <= 16 modes): the aggregates are sums over the
-// segment's particles, so they need no sequential order.  One work-group per
-// (segment, band): lane = slice * wb + mode; a slice takes every nsl-th
-// particle of each block of 64 (nsl = 64 / wb slices), and the slices are
-// added by lane exchanges at the end.
-// ---------------------------------------------------------------------------
-template <typename T, int MH>
-__global__ __launch_bounds__(64) void k_agg_narrow(const KArgs<T> a) {
-    using U = typename Tr<T>::U;
-    const int lane = threadIdx.x;
-    const int seg = blockIdx.x;
-    const Unit un = a.units[blockIdx.y];
-    const int wb = WAVE / un.F, nsl = un.F;
-    const int mi = lane % wb, sl = lane / wb;
+template <int MH, int CPW>
+__global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a) {
+    constexpr int NC = 4 * MH, NCT = (NC + 15) / 16;
+    __shared__ AggLdsH<MH> L;
+    __shared__ float red[AGW_MAX];
+    const int seg = blockIdx.x, tid = threadIdx.x;
+    const int AGW = (int)blockDim.x / WAVE, NT = (int)blockDim.x;
+    const int lane = tid % WAVE, wv = tid / WAVE;
+    const int i = lane & 15, kq = lane >> 4;
     const int64_t i0 = (int64_t)seg * a.S;
     const int n = (int)(min(i0 + (int64_t)a.S, a.N) - i0);
     const int rep = a.seg_rep ? a.seg_rep[seg] : 0;
     const int64_t mb = (int64_t)rep * a.rep_mstride, cb = (int64_t)rep * a.rep_cstride;
-    const bool mv = mi < un.nm;
-    const int m = un.m0 + mi;
-    const int mx = mv ? a.modes[mb + a.moff + m] : 0;
-    const int my = mv ? a.modes[mb + a.mstride + a.moff + m] : 0;
-    const T k = mv ? a.coef[cb + 2 * a.cstride + a.moff + m] : (T)0;
-    __shared__ U c_ux[WAVE], c_uy[WAVE];
-    __shared__ T c_q[WAVE], c_zf[WAVE], c_zb[WAVE];
-    __shared__ cx<T> c_ef[MH][WAVE], c_eb[MH][WAVE];
-    const T zf0 = a.z[i0], zl0 = a.z[i0 + n - 1];
-    cx<T> fx[MH], fy[MH], bx[MH], by[MH];
-#pragma unroll
-    for (int l = 0; l < MH; ++l) fx[l] = fy[l] = bx[l] = by[l] = cx<T>{0, 0};
-    T fkx = 0, fky = 0, bkx = 0, bky = 0;
-    for (int b0 = 0; b0 < n; b0 += WAVE) {
-        __syncthreads();
-        {
-            const int pos = b0 + lane;
-            U ux = 0, uy = 0;
-            T qv = 0, tf = 0, tb = 0;
-            if (pos < n) {
-                ux = a.ux[i0 + pos];
-                uy = a.uy[i0 + pos];
-                qv = a.q[i0 + pos];
-                const T zp = a.z[i0 + pos];
-                tf = zl0 - zp;
-                tb = zp - zf0;
-            }
-            c_ux[lane] = ux;
-            c_uy[lane] = uy;
-            c_q[lane] = qv;
-            c_zf[lane] = tf;
-            c_zb[lane] = tb;
-#pragma unroll
-            for (int l = 0; l < MH; ++l) {
-                c_ef[l][lane] = cexpm(a.bre[l], a.bim[l], tf);
-                c_eb[l][lane] = cexpm(a.bre[l], a.bim[l], tb);
-            }
-        }
-        __syncthreads();
-        for (int j = sl; j < WAVE; j += nsl) {
-            T sn, cs;
-            phase_sc(mx, my, c_ux[j], c_uy[j], sn, cs);
-            const T x = c_q[j] * cs, y = c_q[j] * sn;
-            const T ef = expm_real(k, c_zf[j]), eb = expm_real(k, c_zb[j]);
-            fkx += x * ef;
-            fky += y * ef;
-            bkx += x * eb;
-            bky += y * eb;
-#pragma unroll
-            for (int l = 0; l < MH; ++l) {
-                const cx<T> e = c_ef[l][j];
-                fx[l].re += x * e.re;
-                fx[l].im += x * e.im;
-                fy[l].re += y * e.re;
-                fy[l].im += y * e.im;
-                const cx<T> e2 = c_eb[l][j];
-                bx[l].re += x * e2.re;
-                bx[l].im += x * e2.im;
-                by[l].re += y * e2.re;
-                by[l].im += y * e2.im;
-            }
-        }
+    for (int e = tid; e < (AggLdsH<MH>::NCP - NC) * WAVE; e += NT) {
+        L.eh[NC + e / WAVE][e % WAVE] = (_Float16)0.f;
+        L.el[NC + e / WAVE][e % WAVE] = (_Float16)0.f;
     }
-    // add the slices: lanes mi, mi + wb, mi + 2 wb, ...
-    for (int off = wb; off < WAVE; off <<= 1) {
+    const float s_zf = a.z[i0], s_zl = a.z[i0 + n - 1];
+    // source scale 2^-e with max |q| of the segment < 2^e
+    float qm = 0.f;
+    for (int j = tid; j < n; j += NT) qm = fmaxf(qm, fabsf(a.q[i0 + j]));
 #pragma unroll
-        for (int l = 0; l < MH; ++l) {
-            fx[l].re += __shfl_xor(fx[l].re, off);
-            fx[l].im += __shfl_xor(fx[l].im, off);
-            fy[l].re += __shfl_xor(fy[l].re, off);
-            fy[l].im += __shfl_xor(fy[l].im, off);
-            bx[l].re += __shfl_xor(bx[l].re, off);
-            bx[l].im += __shfl_xor(bx[l].im, off);
-            by[l].re += __shfl_xor(by[l].re, off);
-            by[l].im += __shfl_xor(by[l].im, off);
-        }
-        fkx += __shfl_xor(fkx, off);
-        fky += __shfl_xor(fky, off);
-        bkx += __shfl_xor(bkx, off);
-        bky += __shfl_xor(bky, off);
-    }
-    if (sl == 0 && m < a.gpad) {
+    for (int off = 1; off < WAVE; off <<= 1) qm = fmaxf(qm, __shfl_xor(qm, off));
+    if (lane == 0) red[wv] = qm;
+    __syncthreads();
+    for (int w = 0; w < AGW; ++w) qm = fmaxf(qm, red[w]);
+    int qe = 0;
+    if (qm > 0.f) (void)frexpf(qm, &qe);
+    qe = min(qe, 120);
+    const float qscale = ldexpf(1.f, -qe), qunscale = ldexpf(1.f, qe);
+    const int nblk = (n + WAVE - 1) / WAVE;
+    const int nchunk = (a.nmodes + 15) / 16;  // every column a sweep lane reads
+    const int npass = (nchunk + AGW * CPW - 1) / (AGW * CPW);
+    for (int ps = 0; ps < npass; ++ps) {
+        const int c0 = (ps * AGW + wv) * CPW;  // this wave's first chunk (wave-uniform)
+        const bool act = c0 < nchunk;
+        int pmx[CPW], pmy[CPW];
+        float pk[CPW];
 #pragma unroll
-        for (int l = 0; l < MH; ++l) {
-            a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, l, 0, m)] = fx[l];
-            a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, l, 1, m)] = fy[l];
-            a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, l, 0, m)] = bx[l];
-            a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, l, 1, m)] = by[l];
+        for (int cc = 0; cc < CPW; ++cc) {
+            const int m = 16 * (c0 + cc) + i;
+            const bool mv = m < a.nmodes;
+            pmx[cc] = mv ? a.modes[mb + a.moff + m] : 0;
+            pmy[cc] = mv ? a.modes[mb + a.mstride + a.moff + m] : 0;
+            pk[cc] = mv ? a.coef[cb + 2 * a.cstride + a.moff + m] : 0.f;
         }
-        a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 0, m)] = cx<T>{fkx, 0};
-        a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 1, m)] = cx<T>{fky, 0};
-        a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 0, m)] = cx<T>{bkx, 0};
-        a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 1, m)] = cx<T>{bky, 0};
+        f4v acc[2 * CPW][NCT];
+#pragma unroll
+        for (int t = 0; t < 2 * CPW; ++t)
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) acc[t][c] = f4v{0.f, 0.f, 0.f, 0.f};
+        float fk[CPW][4];
+#pragma unroll
+        for (int cc = 0; cc < CPW; ++cc) fk[cc][0] = fk[cc][1] = fk[cc][2] = fk[cc][3] = 0.f;
+        for (int blk = 0; blk < nblk; ++blk) {
+            __syncthreads();
+            {
+                // particle lane of the block; wave wv stages pairs wv, wv + AGW, ...
+                const int pos = blk * WAVE + lane;
+                float tf = 0.f, tb = 0.f;
+                if (pos < n) {
+                    const float zp = a.z[i0 + pos];
+                    tf = s_zl - zp;
+                    tb = zp - s_zf;
+                }
+                if (wv == 0) {
+                    uint32_t ux = 0, uy = 0;
+                    float qv = 0.f;
+                    if (pos < n) {
+                        ux = a.ux[i0 + pos];
+                        uy = a.uy[i0 + pos];
+                        qv = a.q[i0 + pos] * qscale;
+                    }
+                    L.ux[lane] = ux;
+                    L.uy[lane] = uy;
+                    L.q[lane] = qv;
+                    L.zf[lane] = tf;
+                    L.zb[lane] = tb;
+                }
+                for (int l = wv; l < MH; l += AGW) {
+                    const cx<float> ef = cexpm(a.bre[l], a.bim[l], tf);
+                    const cx<float> eb = cexpm(a.bre[l], a.bim[l], tb);
+                    const float v4[4] = {ef.re, ef.im, eb.re, eb.im};
+                    const int cols[4] = {2 * l, 2 * l + 1, 2 * MH + 2 * l, 2 * MH + 2 * l + 1};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const _Float16 h = (_Float16)v4[u];
+                        L.eh[cols[u]][lane] = h;
+                        L.el[cols[u]][lane] = (_Float16)(v4[u] - (float)h);
+                    }
+                }
+            }
+            __syncthreads();
+            if (!act) continue;
+#pragma unroll 1
+            for (int ks = 0; ks < 2; ++ks) {
+                const int e0 = 32 * ks + 8 * kq;  // this lane's 8 particles
+                h8v bh[NCT], bl[NCT];
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) {
+                    bh[c] = *(const h8v *)&L.eh[16 * c + i][e0];
+                    bl[c] = *(const h8v *)&L.el[16 * c + i][e0];
+                }
+#pragma unroll
+                for (int cc = 0; cc < CPW; ++cc) {
+                    float xs[8], ys[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        float sn, cs;
+                        phase_sc(pmx[cc], pmy[cc], L.ux[e0 + e], L.uy[e0 + e], sn, cs);
+                        const float qv = L.q[e0 + e];
+                        xs[e] = qv * cs;
+                        ys[e] = qv * sn;
+                        const float ef = __expf(-pk[cc] * L.zf[e0 + e]);
+                        const float eb = __expf(-pk[cc] * L.zb[e0 + e]);
+                        fk[cc][0] = fma(xs[e], ef, fk[cc][0]);
+                        fk[cc][1] = fma(ys[e], ef, fk[cc][1]);
+                        fk[cc][2] = fma(xs[e], eb, fk[cc][2]);
+                        fk[cc][3] = fma(ys[e], eb, fk[cc][3]);
+                    }
+                    h8v xh, xl, yh, yl;
+                    split8(xs, xh, xl);
+                    split8(ys, yh, yl);
+#pragma unroll
+                    for (int c = 0; c < NCT; ++c) {
+                        f4v &ax = acc[cc][c], &ay = acc[CPW + cc][c];
+                        ax = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, bh[c], ax, 0, 0, 0);
+                        ax = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, bl[c], ax, 0, 0, 0);
+                        ax = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl, bh[c], ax, 0, 0, 0);
+                        ay = __builtin_amdgcn_mfma_f32_16x16x32_f16(yh, bh[c], ay, 0, 0, 0);
+                        ay = __builtin_amdgcn_mfma_f32_16x16x32_f16(yh, bl[c], ay, 0, 0, 0);
+                        ay = __builtin_amdgcn_mfma_f32_16x16x32_f16(yl, bh[c], ay, 0, 0, 0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+        if (!act) continue;
+        // tile (source inp, chunk cc), column tile c, register v -> mode
+        // 16 (c0 + cc) + 4 kq + v, column 16 c + i (sources scaled back)
+        float *aggf = (float *)a.agg;
+#pragma unroll
+        for (int cc = 0; cc < CPW; ++cc)
+#pragma unroll
+            for (int inp = 0; inp < 2; ++inp)
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) {
+                    const int col = 16 * c + i;
+                    if (col >= NC) continue;
+                    const int dir = col / (2 * MH), slot = (col % (2 * MH)) / 2, ri = col % 2;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int m = 16 * (c0 + cc) + 4 * kq + v;
+                        if (m < a.gpad)
+                            aggf[2 * agg_idx<MH>(a.nseg, a.gpad, dir, seg, slot, inp, m) + ri] =
+                                acc[inp * CPW + cc][c][v] * qunscale;
+                    }
+                }
+        // beta = k term: add the four particle quarters (lanes i, i+16, i+32, i+48)
+#pragma unroll
+        for (int cc = 0; cc < CPW; ++cc)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                float v = fk[cc][w];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                fk[cc][w] = v * qunscale;
+            }
+        if (kq == 0) {
+#pragma unroll
+            for (int cc = 0; cc < CPW; ++cc) {
+                const int m = 16 * (c0 + cc) + i;
+                if (m < a.gpad) {
+                    a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 0, m)] = cx<float>{fk[cc][0], 0.f};
+                    a.agg[agg_idx<MH>(a.nseg, a.gpad, 0, seg, MH, 1, m)] = cx<float>{fk[cc][1], 0.f};
+                    a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 0, m)] = cx<float>{fk[cc][2], 0.f};
+                    a.agg[agg_idx<MH>(a.nseg, a.gpad, 1, seg, MH, 1, m)] = cx<float>{fk[cc][3], 0.f};
+                }
+            }
+        }
     }
 }
 
@@ -1125,11 +1042,15 @@ void dispatch_sweep(Plan *p, const KArgs<T> &ka, dim3 grid) {
     }
 }
 
-void dispatch_agg_mfma(Plan *p, const KArgs<float> &ka, dim3 grid) {
+void dispatch_agg_seg(Plan *p, const KArgs<float> &ka) {
+    // AGG_CPW chunks of 16 modes per wave, as many waves as that takes (at
+    // most AGW_MAX; more chunks take several passes over the segment)
+    const int nchunk = (ka.nmodes + 15) / 16;
+    const int nw = std::max(1, std::min(AGW_MAX, (nchunk + AGG_CPW - 1) / AGG_CPW));
     switch (p->mh) {
-#define Q2D_CASE(n)                                                   \
-    case n:                                                           \
-        k_agg_mfma<n><<<grid, WAVE, 0, p->stream>>>(ka);              \
+#define Q2D_CASE(n)                                                            \
+    case n:                                                                    \
+        k_agg_seg<n, AGG_CPW><<<ka.nseg, nw * WAVE, 0, p->stream>>>(ka);       \
         break;
         Q2D_CASE(1) Q2D_CASE(2) Q2D_CASE(3) Q2D_CASE(4) Q2D_CASE(5) Q2D_CASE(6) Q2D_CASE(7)
         Q2D_CASE(8) Q2D_CASE(9) Q2D_CASE(10) Q2D_CASE(11) Q2D_CASE(12)
@@ -1139,49 +1060,14 @@ void dispatch_agg_mfma(Plan *p, const KArgs<float> &ka, dim3 grid) {
     }
 }
 
-// Pass 1 for a launch's units: FP32 units with >= 32 modes per segment group
-// (F <= 2) on the matrix cores, the others on the VALU, each launch with its
-// own numbering of the work-groups.
-template <typename T>
-void dispatch_agg_narrow(Plan *p, const KArgs<T> &ka, dim3 grid) {
-    switch (p->mh) {
-#define Q2D_CASE(n)                                                   \
-    case n:                                                           \
-        k_agg_narrow<T, n><<<grid, WAVE, 0, p->stream>>>(ka);         \
-        break;
-        Q2D_CASE(1) Q2D_CASE(2) Q2D_CASE(3) Q2D_CASE(4) Q2D_CASE(5) Q2D_CASE(6) Q2D_CASE(7)
-        Q2D_CASE(8) Q2D_CASE(9) Q2D_CASE(10) Q2D_CASE(11) Q2D_CASE(12) Q2D_CASE(13)
-        Q2D_CASE(14) Q2D_CASE(15) Q2D_CASE(16)
-#undef Q2D_CASE
-        default:
-            break;
-    }
-}
-
-// Pass 1 for a launch's units.  FP32 with M <= 24: units with >= 32 modes per
-// segment group (F <= 2) on the matrix cores, and narrow bands (F >= 4) with
-// one work-group per (segment, band).  Otherwise the VALU kernel over the
-// launch's own layout.
+// Pass 1 for a launch.  FP32 with M <= 24: the per-segment split-fp16 matrix
+// kernel over all the launch's modes; otherwise the VALU kernel over the
+// launch's units.
 template <typename T>
 void launch_agg(Plan *p, const KArgs<T> &ka, int blocks) {
     if constexpr (std::is_same<T, float>::value) {
         if (p->mh <= 12) {
-            KArgs<float> km = ka, kn = ka;
-            int nm = 0, nn = 0, bm = 0;
-            for (int u = 0; u < ka.nunits; ++u) {
-                Unit un = ka.units[u];
-                if (un.F <= 2) {
-                    un.b0 = bm;
-                    km.units[nm++] = un;
-                    bm += (ka.nseg + un.F - 1) / un.F;
-                } else {
-                    kn.units[nn++] = un;
-                }
-            }
-            km.nunits = nm;
-            kn.nunits = nn;
-            if (nn) dispatch_agg_narrow<float>(p, kn, dim3(ka.nseg, nn));
-            if (bm) dispatch_agg_mfma(p, km, dim3(bm));
+            dispatch_agg_seg(p, ka);
             return;
         }
     }
