@@ -845,37 +845,48 @@ struct Decay {
 // Walk the segments of one range in the direction of propagation starting from
 // carry c: forward CF_{s+1} = G_s (AF_s + W_s CF_s), backward
 // CB_{s-1} = G_{s-1} (AB_s + W_s CB_s).  WRITE: store each segment's carry-in
-// in place of its aggregate.  Returns the carry out and the range's total decay.
+// in place of its aggregate; otherwise also accumulate the range's total
+// decay D, so that the range maps x -> c + D x.
+// Both directions are walked in one loop (the forward chain upwards, the
+// backward chain downwards): their loads are issued together, which doubles
+// the memory-level parallelism of these latency-bound walks.  c[d], D[d]:
+// carry and decay of direction d.
 template <typename T, bool KMODE, bool WRITE>
-__device__ inline void walk(const CArgs<T> &a, const Decay<T, KMODE> &dc, int dir, int col,
-                            int s0, int s1, cx<double> &c, cx<double> &D) {
-    cx<T> *AG = a.agg + (dir ? (int64_t)a.nseg * a.ncols : 0);
+__device__ inline void walk2(const CArgs<T> &a, const Decay<T, KMODE> &dc, int col, int s0,
+                             int s1, cx<double> (&c)[2], cx<double> (&D)[2]) {
+    cx<T> *AG[2] = {a.agg, a.agg + (int64_t)a.nseg * a.ncols};
     const int n = s1 - s0;
     for (int k0 = 0; k0 < n; k0 += CAR_BATCH) {
-        cx<T> av[CAR_BATCH];
-        cx<double> W[CAR_BATCH], G[CAR_BATCH];
+        cx<T> av[2][CAR_BATCH];
+        cx<double> W[2][CAR_BATCH], G[2][CAR_BATCH];
 #pragma unroll
         for (int u = 0; u < CAR_BATCH; ++u) {
             const int k = k0 + u;
             if (k < n) {
-                const int s = dir ? s1 - 1 - k : s0 + k;
-                dc.step(dir, s, W[u], G[u]);
-                av[u] = AG[(int64_t)s * a.ncols + col];
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const int s = d ? s1 - 1 - k : s0 + k;
+                    dc.step(d, s, W[d][u], G[d][u]);
+                    av[d][u] = AG[d][(int64_t)s * a.ncols + col];
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < CAR_BATCH; ++u) {
             const int k = k0 + u;
             if (k < n) {
-                if (WRITE) {
-                    const int s = dir ? s1 - 1 - k : s0 + k;
-                    AG[(int64_t)s * a.ncols + col] = cx<T>{(T)c.re, (T)c.im};
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    if (WRITE) {
+                        const int s = d ? s1 - 1 - k : s0 + k;
+                        AG[d][(int64_t)s * a.ncols + col] = cx<T>{(T)c[d].re, (T)c[d].im};
+                    }
+                    cx<double> t = cmul(W[d][u], c[d]);
+                    t.re += (double)av[d][u].re;
+                    t.im += (double)av[d][u].im;
+                    c[d] = cmul(G[d][u], t);
+                    if (!WRITE) D[d] = cmul(G[d][u], cmul(W[d][u], D[d]));
                 }
-                cx<double> t = cmul(W[u], c);
-                t.re += (double)av[u].re;
-                t.im += (double)av[u].im;
-                c = cmul(G[u], t);
-                if (!WRITE) D = cmul(G[u], cmul(W[u], D));
             }
         }
     }
@@ -889,12 +900,13 @@ __global__ __launch_bounds__(256) void k_cfold(const CArgs<T> a, int nr, cx<doub
     const int col = (int)(t % a.ncols), r = (int)(t / a.ncols);
     const int s0 = r * CAR_L, s1 = min(s0 + CAR_L, a.nseg);
     const Decay<T, KMODE> dc(a, col);
+    cx<double> c[2] = {{0.0, 0.0}, {0.0, 0.0}}, D[2] = {{1.0, 0.0}, {1.0, 0.0}};
+    walk2<T, KMODE, false>(a, dc, col, s0, s1, c, D);
+#pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
-        cx<double> c{0.0, 0.0}, D{1.0, 0.0};
-        walk<T, KMODE, false>(a, dc, dir, col, s0, s1, c, D);
         const int64_t o = (((int64_t)dir * a.ncols + col) * nr + r) * 2;
-        rc[o] = c;
-        rc[o + 1] = D;
+        rc[o] = c[dir];
+        rc[o + 1] = D[dir];
     }
 }
 
@@ -963,10 +975,10 @@ __global__ __launch_bounds__(256) void k_capply(const CArgs<T> a, int nr, const 
     const int col = (int)(t % a.ncols), r = (int)(t / a.ncols);
     const int s0 = r * CAR_L, s1 = min(s0 + CAR_L, a.nseg);
     const Decay<T, KMODE> dc(a, col);
-    for (int dir = 0; dir < 2; ++dir) {
-        cx<double> c = rc[(((int64_t)dir * a.ncols + col) * nr + r) * 2], D{1.0, 0.0};
-        walk<T, KMODE, true>(a, dc, dir, col, s0, s1, c, D);
-    }
+    cx<double> c[2], D[2] = {{1.0, 0.0}, {1.0, 0.0}};
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) c[dir] = rc[(((int64_t)dir * a.ncols + col) * nr + r) * 2];
+    walk2<T, KMODE, true>(a, dc, col, s0, s1, c, D);
 }
 
 template <typename T, bool KMODE>
