@@ -459,7 +459,7 @@ void plan_release(Plan *p) {
                    &p->agg0, &p->carry_tmp0, &p->phi0, &p->fz0, &p->epart, &p->inv, &p->status,
                    &p->cell_start, &p->cell_count, &p->cell_idx, &p->cell_tmp, &p->rep_box,
                    &p->rep_H, &p->rep_diag, &p->rep_tpa, &p->rep_of, &p->rep_off, &p->rep_poff,
-                   &p->seg_rep, &p->pperm, &p->epart_rep, &p->step_ctr};
+                   &p->seg_rep, &p->pperm, &p->epart_rep, &p->step_ctr, &p->recs};
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     p->graph_exec = nullptr;

@@ -92,6 +92,7 @@ struct Plan {
 
     // sorting and sorted data
     Buf keys_a, keys_b, vals_a, vals_b, hist;
+    Buf recs;                  // (x, y, z, q) records in input order, for the gather
     Buf s_ux, s_uy, s_z, s_q;  // sorted SoA
     int32_t *perm = nullptr;   // points into vals_a or vals_b after the sort
     // sources of the scans: sorted q unless set (the adjoint pass points it at s_g)

@@ -101,6 +101,13 @@ __device__ inline cx<double> cexpm(double br, double bi, double t) {
     sincos(ai, &s, &c);
     return {m * c, -m * s};
 }
+// e^{-beta t} for the spans tables (FP64: the carries are built from them)
+__device__ inline cx<double> span_decay(double br, double bi, double t) {
+    double sn, cs;
+    sincos(bi * t, &sn, &cs);
+    const double m = exp(-br * t);
+    return {m * cs, -m * sn};
+}
 __device__ inline float expm_real(float k, float t) { return __expf(-k * t); }
 __device__ inline double expm_real(double k, double t) { return exp(-k * t); }
 
@@ -340,11 +347,20 @@ __device__ inline void split8(const float (&v)[8], h8v &hi, h8v &lo) {
 constexpr int AGW_MAX = 8;  // waves per work-group at most
 constexpr int AGG_CPW = 2;  // 16-mode chunks per wave (measured best of 1, 2, 4)
 
+// the FP64 betas and the spans table (W, G per (segment, pair)) that the
+// aggregate kernel fills for the carry scan
+struct SpanArgs {
+    double br[MAX_PAIRS], bi[MAX_PAIRS];
+    cx<double> *spans;
+};
+
 template <int MH, int CPW>
-__global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a) {
+__global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a,
+                                                           const SpanArgs sp) {
     constexpr int NC = 4 * MH, NCT = (NC + 15) / 16;
     __shared__ AggLdsH<MH> L;
     __shared__ float red[AGW_MAX];
+    __shared__ double sb[2][MH];
     const int seg = blockIdx.x, tid = threadIdx.x;
     const int AGW = (int)blockDim.x / WAVE, NT = (int)blockDim.x;
     const int lane = tid % WAVE, wv = tid / WAVE;
@@ -364,7 +380,24 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
 #pragma unroll
     for (int off = 1; off < WAVE; off <<= 1) qm = fmaxf(qm, __shfl_xor(qm, off));
     if (lane == 0) red[wv] = qm;
+    if (tid == 0) {
+        // uniform indices (a lane-dependent index into the arguments would
+        // compile to select chains)
+        for (int l = 0; l < MH; ++l) {
+            sb[0][l] = sp.br[l];
+            sb[1][l] = sp.bi[l];
+        }
+    }
     __syncthreads();
+    if (tid < 2 * MH) {
+        // this segment's spans: W = e^{-beta (z_last - z_first)}, G = e^{-beta
+        // (z_first(next) - z_last)} (the same values as k_spans)
+        const int l = tid >> 1, wg = tid & 1;
+        const double zf = (double)s_zf, zl = (double)s_zl;
+        const double zn = seg + 1 < a.nseg ? (double)a.z[i0 + a.S] : zl;
+        sp.spans[((int64_t)seg * MH + l) * 2 + wg] =
+            span_decay(sb[0][l], sb[1][l], wg ? zn - zl : zl - zf);
+    }
     for (int w = 0; w < AGW; ++w) qm = fmaxf(qm, red[w]);
     int qe = 0;
     if (qm > 0.f) (void)frexpf(qm, &qe);
@@ -1013,13 +1046,8 @@ __global__ __launch_bounds__(256) void k_spans(const T *__restrict__ z, int64_t 
     const double zf = (double)z[b], zl = (double)z[e];
     const double zn = (s + 1 < nseg) ? (double)z[(int64_t)(s + 1) * S] : zl;
     const double br = pp.beta_re[l], bi = pp.beta_im[l];
-    double sn, cs;
-    sincos(bi * (zl - zf), &sn, &cs);
-    double m = exp(-br * (zl - zf));
-    spans[idx * 2] = cx<double>{m * cs, -m * sn};
-    sincos(bi * (zn - zl), &sn, &cs);
-    m = exp(-br * (zn - zl));
-    spans[idx * 2 + 1] = cx<double>{m * cs, -m * sn};
+    spans[idx * 2] = span_decay(br, bi, zl - zf);
+    spans[idx * 2 + 1] = span_decay(br, bi, zn - zl);
 }
 
 template <typename T>
@@ -1054,7 +1082,7 @@ void dispatch_sweep(Plan *p, const KArgs<T> &ka, dim3 grid) {
     }
 }
 
-void dispatch_agg_seg(Plan *p, const KArgs<float> &ka) {
+void dispatch_agg_seg(Plan *p, const KArgs<float> &ka, const SpanArgs &sp) {
     // AGG_CPW chunks of 16 modes per wave, as many waves as that takes (at
     // most AGW_MAX; more chunks take several passes over the segment)
     const int nchunk = (ka.nmodes + 15) / 16;
@@ -1062,7 +1090,7 @@ void dispatch_agg_seg(Plan *p, const KArgs<float> &ka) {
     switch (p->mh) {
 #define Q2D_CASE(n)                                                            \
     case n:                                                                    \
-        k_agg_seg<n, AGG_CPW><<<ka.nseg, nw * WAVE, 0, p->stream>>>(ka);       \
+        k_agg_seg<n, AGG_CPW><<<ka.nseg, nw * WAVE, 0, p->stream>>>(ka, sp);   \
         break;
         Q2D_CASE(1) Q2D_CASE(2) Q2D_CASE(3) Q2D_CASE(4) Q2D_CASE(5) Q2D_CASE(6) Q2D_CASE(7)
         Q2D_CASE(8) Q2D_CASE(9) Q2D_CASE(10) Q2D_CASE(11) Q2D_CASE(12)
@@ -1075,11 +1103,23 @@ void dispatch_agg_seg(Plan *p, const KArgs<float> &ka) {
 // Pass 1 for a launch.  FP32 with M <= 24: the per-segment split-fp16 matrix
 // kernel over all the launch's modes; otherwise the VALU kernel over the
 // launch's units.
+// true if launch_agg fills the spans table itself
+template <typename T>
+bool agg_fills_spans(const Plan *p) {
+    return std::is_same<T, float>::value && p->mh <= 12;
+}
+
 template <typename T>
 void launch_agg(Plan *p, const KArgs<T> &ka, int blocks) {
     if constexpr (std::is_same<T, float>::value) {
-        if (p->mh <= 12) {
-            dispatch_agg_seg(p, ka);
+        if (agg_fills_spans<T>(p)) {
+            SpanArgs sp{};
+            for (int l = 0; l < p->mh; ++l) {
+                sp.br[l] = p->pp.beta_re[l];
+                sp.bi[l] = p->pp.beta_im[l];
+            }
+            sp.spans = (cx<double> *)p->spans.p;
+            dispatch_agg_seg(p, ka, sp);
             return;
         }
     }
@@ -1146,7 +1186,7 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         Q2D_OK)
         return st;
     if ((st = ensure(p, p->outk, (size_t)nchunks * N * 4 * sizeof(T))) != Q2D_OK) return st;
-    {
+    if (!agg_fills_spans<T>(p)) {
         const int64_t n = (int64_t)nseg * mh;
         k_spans<T><<<(int)((n + 255) / 256), 256, 0, p->stream>>>((const T *)p->s_z.p, N, S, nseg,
                                                                    p->pp, (cx<double> *)p->spans.p);

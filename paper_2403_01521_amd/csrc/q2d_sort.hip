@@ -27,17 +27,25 @@ __device__ inline uint64_t zkey(double z) {
 // Status bits in the device status word (bit q2d_status).
 __device__ inline void set_status(int *st, int code) { atomicOr(st, 1 << code); }
 
+// one particle's position and charge in one aligned record: the gather after
+// the sort then reads one record per particle instead of two scattered ones
+template <typename T>
+struct alignas(4 * sizeof(T)) Rec {
+    T x, y, z, q;
+};
+
 template <typename T, typename K>
 __global__ __launch_bounds__(256) void k_stage(const T *__restrict__ pos, const T *__restrict__ q,
                                                int64_t N, K *__restrict__ keys,
-                                               int32_t *__restrict__ vals, double Lz,
-                                               int validate, int *status, double *qsums) {
+                                               int32_t *__restrict__ vals, Rec<T> *__restrict__ rec,
+                                               double Lz, int validate, int *status, double *qsums) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double qv = 0.0;
     if (i < N) {
         const T z = pos[3 * i + 2];
         keys[i] = zkey(z);
         vals[i] = (int32_t)i;
+        rec[i] = Rec<T>{pos[3 * i], pos[3 * i + 1], z, q[i]};
         if (validate) {
             const T x = pos[3 * i], y = pos[3 * i + 1];
             qv = (double)q[i];
@@ -212,8 +220,7 @@ struct Fix<double> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gather(const T *__restrict__ pos,
-                                                const T *__restrict__ q,
+__global__ __launch_bounds__(256) void k_gather(const Rec<T> *__restrict__ rec,
                                                 const int32_t *__restrict__ perm, int64_t N,
                                                 double Lx, double Ly,
                                                 typename Fix<T>::U *__restrict__ ux,
@@ -221,11 +228,11 @@ __global__ __launch_bounds__(256) void k_gather(const T *__restrict__ pos,
                                                 T *__restrict__ zs, T *__restrict__ qs) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const int64_t o = perm[i];
-    ux[i] = Fix<T>::frac((double)pos[3 * o] / Lx);
-    uy[i] = Fix<T>::frac((double)pos[3 * o + 1] / Ly);
-    zs[i] = pos[3 * o + 2] + (T)0;
-    qs[i] = q[o];
+    const Rec<T> r = rec[perm[i]];
+    ux[i] = Fix<T>::frac((double)r.x / Lx);
+    uy[i] = Fix<T>::frac((double)r.y / Ly);
+    zs[i] = r.z + (T)0;
+    qs[i] = r.q;
 }
 
 template <typename T>
@@ -253,13 +260,15 @@ q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
     if ((st = ensure(p, p->s_uy, N * sizeof(U))) != Q2D_OK) return st;
     if ((st = ensure(p, p->s_z, N * sizeof(T))) != Q2D_OK) return st;
     if ((st = ensure(p, p->s_q, N * sizeof(T))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->recs, N * sizeof(Rec<T>))) != Q2D_OK) return st;
 
     int *status = (int *)p->status.p;
     double *qsums = (double *)((char *)p->status.p + 16);
     const int nb = (int)((N + 255) / 256);
     if (p->opts.validate) k_zero2<<<1, 1, 0, p->stream>>>(qsums);
     k_stage<T, K><<<nb, 256, 0, p->stream>>>(pos, q, N, (K *)p->keys_a.p, (int32_t *)p->vals_a.p,
-                                             p->Lz, p->opts.validate, status, qsums);
+                                             (Rec<T> *)p->recs.p, p->Lz, p->opts.validate, status,
+                                             qsums);
     if (p->opts.validate) k_neutral_check<<<1, 1, 0, p->stream>>>(qsums, status);
 
     uint32_t *hist = (uint32_t *)p->hist.p;
@@ -277,8 +286,9 @@ q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
         std::swap(vin, vout);
     }
     p->perm = vin;
-    k_gather<T><<<nb, 256, 0, p->stream>>>(pos, q, p->perm, N, p->Lx, p->Ly, (U *)p->s_ux.p,
-                                           (U *)p->s_uy.p, (T *)p->s_z.p, (T *)p->s_q.p);
+    k_gather<T><<<nb, 256, 0, p->stream>>>((const Rec<T> *)p->recs.p, p->perm, N, p->Lx, p->Ly,
+                                           (U *)p->s_ux.p, (U *)p->s_uy.p, (T *)p->s_z.p,
+                                           (T *)p->s_q.p);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
