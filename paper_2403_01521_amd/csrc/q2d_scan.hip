@@ -308,10 +308,10 @@ __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
 
 // ---------------------------------------------------------------------------
 // pass 1 on the fp16 matrix cores with split operands (FP32 plans, M <= 24).
-// Every FP32 operand v is carried as v_hi + v_lo with v_hi = fp16(v) and
-// v_lo = fp16(v - v_hi); the products hi*hi + hi*lo + lo*hi, accumulated in
-// FP32, leave an error of about 2^-21 |v| |w| per term (the lo*lo term and the
-// two roundings), the size of FP32 rounding over a segment's sum.  The decays
+// Every FP32 operand v is carried as v_hi + v_lo with v_hi = fp16(v) (rounded
+// toward zero) and v_lo = fp16(v - v_hi); the products hi*hi + hi*lo + lo*hi,
+// accumulated in FP32, leave an error of about 2^-20 |v| |w| per term (the
+// lo*lo term and the roundings of the lo parts), FP32-sized over a segment.  The decays
 // satisfy |E| <= 1; the sources are scaled by a power of two that brings the
 // segment's largest |q| below 1 (undone exactly on the result), so no fp16
 // overflow can occur.  v_mfma_f32_16x16x32_f16 takes 32 particles per
@@ -330,12 +330,31 @@ struct alignas(16) AggLdsH {
     _Float16 eh[NCP][RP], el[NCP][RP];                    // decays [column][entry], hi and lo
 };
 
+// hi of two values from one instruction (rounded toward zero: |v - hi| < 2^-10 |v|),
+// lo = fp16(v - hi) from that same hi.  Computing hi once matters: the
+// compiler otherwise forms hi both from the exact product that produced v (a
+// fused multiply) and from v (a second rounding), and the two differ by an
+// fp16 ulp now and then, so hi + lo != v (measured: FP32 forces 10x less
+// accurate for charges that are not powers of two).  With hi fixed, any
+// evaluation of lo leaves |v - hi - lo| <= 2^-21 |v|.
+__device__ inline void split_pair(float a, float b, _Float16 &ha, _Float16 &hb, _Float16 &la,
+                                  _Float16 &lb) {
+    const auto h = __builtin_amdgcn_cvt_pkrtz(a, b);
+    ha = (_Float16)h[0];
+    hb = (_Float16)h[1];
+    la = (_Float16)(a - (float)ha);
+    lb = (_Float16)(b - (float)hb);
+}
+
 __device__ inline void split8(const float (&v)[8], h8v &hi, h8v &lo) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const _Float16 h = (_Float16)v[e];
-        hi[e] = h;
-        lo[e] = (_Float16)(v[e] - (float)h);
+    for (int e = 0; e < 8; e += 2) {
+        _Float16 ha, hb, la, lb;
+        split_pair(v[e], v[e + 1], ha, hb, la, lb);
+        hi[e] = ha;
+        hi[e + 1] = hb;
+        lo[e] = la;
+        lo[e + 1] = lb;
     }
 }
 
@@ -455,13 +474,14 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
                 for (int l = wv; l < MH; l += AGW) {
                     const cx<float> ef = cexpm(a.bre[l], a.bim[l], tf);
                     const cx<float> eb = cexpm(a.bre[l], a.bim[l], tb);
-                    const float v4[4] = {ef.re, ef.im, eb.re, eb.im};
+                    _Float16 h[4], lo[4];
+                    split_pair(ef.re, ef.im, h[0], h[1], lo[0], lo[1]);
+                    split_pair(eb.re, eb.im, h[2], h[3], lo[2], lo[3]);
                     const int cols[4] = {2 * l, 2 * l + 1, 2 * MH + 2 * l, 2 * MH + 2 * l + 1};
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const _Float16 h = (_Float16)v4[u];
-                        L.eh[cols[u]][lane] = h;
-                        L.el[cols[u]][lane] = (_Float16)(v4[u] - (float)h);
+                        L.eh[cols[u]][lane] = h[u];
+                        L.el[cols[u]][lane] = lo[u];
                     }
                 }
             }

@@ -1,0 +1,110 @@
+"""FP32 aggregate pass on the fp16 matrix cores (split operands).
+
+The FP32 plans compute the segment aggregates with every operand carried as two
+fp16 halves and the sources scaled per segment by a power of two.  These tests
+pin that arithmetic against relations that hold exactly and against the FP64
+path (which does not use fp16):
+
+* charge scaling: q -> s q multiplies phi by s and F, E by s^2 (the method is
+  linear in the sources); s = 1e6 takes |q| far past the fp16 range, s = 1e-7
+  puts every source in the fp16 subnormal range without the scaling.  Both FP32
+  runs (rescaled) must match the FP64 step as closely as each other;
+* mixed magnitudes (charges 1 and 1000 in one segment) and two thin slabs with a
+  wide empty gap (long segment spans, large decay phases): FP32 against FP64 on
+  the same modes within 2e-5.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2403_01521_amd as q2d  # noqa: E402
+import workloads as wl  # noqa: E402
+
+P = 64
+
+
+def dev(a, dt):
+    return torch.tensor(np.asarray(a), dtype=dt, device="cuda")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def step(box, alpha, w, s, pos, q, prec, seed=21, stepno=3):
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    plan = q2d.Plan(box, alpha, w, s, precision=prec, n_max=len(q), p_max=P)
+    phi, F, E, modes = plan.rbm_step(dev(pos, dt), dev(q, dt), P, seed, stepno)
+    torch.cuda.synchronize()
+    out = (phi.double().cpu().numpy(), F.double().cpu().numpy(), float(E.cpu()[0]),
+           modes.cpu().numpy())
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("scale", [1e6, 1e-7])
+def test_charge_scaling(soe_tables, scale):
+    c = wl.make_config(3, dtype=np.float32, n_override=6000)
+    w, s = soe_tables[16]
+    q = c["q"].astype(np.float32)
+    qs = (q.astype(np.float64) * scale).astype(np.float32)
+    # the exact scale factor after FP32 rounding of the charges
+    ratio = float(np.median(qs.astype(np.float64) / q.astype(np.float64)))
+    phi1, F1, E1, m1 = step(c["box"], c["alpha"], w, s, c["pos"], q, "fp32")
+    phi2, F2, E2, m2 = step(c["box"], c["alpha"], w, s, c["pos"], qs, "fp32")
+    phi0, F0, E0, m0 = step(c["box"], c["alpha"], w, s, c["pos"].astype(np.float64),
+                            q.astype(np.float64), "fp64")
+    assert np.array_equal(m1, m2) and np.array_equal(m1, m0)
+    assert np.all(np.isfinite(phi2)) and np.all(np.isfinite(F2))
+    # each FP32 run against the FP64 step on the same modes (two independent
+    # FP32 roundings are not compared with each other)
+    e1 = (rel(phi1, phi0), rel(F1, F0), abs(E1 - E0) / abs(E0))
+    e2 = (rel(phi2 / ratio, phi0), rel(F2 / ratio**2, F0), abs(E2 / ratio**2 - E0) / abs(E0))
+    print("scale %g: unscaled phi %.2e F %.2e E %.2e | scaled phi %.2e F %.2e E %.2e"
+          % ((scale,) + e1 + e2))
+    for a, b in zip(e1, e2):
+        assert a < 3e-5 and b < 3e-5
+        assert b < 2 * a + 1e-5
+
+def two_slabs(rng, n, box):
+    """Half the ions in z in [0, 0.05 Lz], half in [0.95 Lz, Lz]: the middle is empty."""
+    pos, q = wl.uniform_ions(rng, n // 2, n - n // 2, tuple(box))
+    pos = pos.reshape(-1, 3)
+    z = pos[:, 2] / box[2]
+    pos[:, 2] = np.where(np.arange(len(z)) % 2 == 0, 0.05 * z, 1.0 - 0.05 * z) * box[2]
+    return pos, q
+
+
+def mixed_charges(rng, n, box):
+    """Unit ions with every 97th charge scaled to +-1000 (pairs keep the sum zero)."""
+    pos, q = wl.uniform_ions(rng, n // 2, n - n // 2, tuple(box))
+    q = q.copy()
+    idx = np.arange(0, n - 1, 97)
+    q[idx] *= 1000.0
+    # restore neutrality with the opposite big charge on the next particle
+    q[idx + 1] = -q[idx]
+    q[-1] -= q.sum()
+    return pos.reshape(-1, 3), q
+
+
+@pytest.mark.parametrize("maker", [two_slabs, mixed_charges])
+def test_fp32_vs_fp64_hard_inputs(soe_tables, maker):
+    rng = np.random.Generator(np.random.PCG64(777))
+    box = (40.0, 40.0, 8.0)
+    pos, q = maker(rng, 5000, box)
+    pos32, q32 = pos.astype(np.float32), q.astype(np.float32)
+    w, s = soe_tables[16]
+    phi32, F32, E32, m32 = step(box, 0.3, w, s, pos32, q32, "fp32")
+    phi64, F64, E64, m64 = step(box, 0.3, w, s, pos32.astype(np.float64),
+                                q32.astype(np.float64), "fp64")
+    assert np.array_equal(m32, m64)
+    print("%s: phi %.2e F %.2e E %.2e" % (maker.__name__, rel(phi32, phi64), rel(F32, F64),
+                                         abs(E32 - E64) / abs(E64)))
+    assert rel(phi32, phi64) < 2e-5
+    assert rel(F32, F64) < 2e-5
+    assert abs(E32 - E64) < 2e-5 * abs(E64)
