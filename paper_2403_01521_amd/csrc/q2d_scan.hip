@@ -945,6 +945,13 @@ __device__ inline void walk2(const CArgs<T> &a, const Decay<T, KMODE> &dc, int c
     }
 }
 
+// The range transfers live in two planes of [2 directions][nr ranges][ncols]
+// complex values, c first, then D: the lanes of a wave (consecutive columns)
+// touch consecutive addresses in all three passes.
+__device__ inline int64_t rc_at(int ncols, int nr, int dir, int r, int col) {
+    return ((int64_t)dir * nr + r) * ncols + col;
+}
+
 // (1) one thread per (column, range): fold the range into x -> c + D x
 template <typename T, bool KMODE>
 __global__ __launch_bounds__(256) void k_cfold(const CArgs<T> a, int nr, cx<double> *rc) {
@@ -955,61 +962,67 @@ __global__ __launch_bounds__(256) void k_cfold(const CArgs<T> a, int nr, cx<doub
     const Decay<T, KMODE> dc(a, col);
     cx<double> c[2] = {{0.0, 0.0}, {0.0, 0.0}}, D[2] = {{1.0, 0.0}, {1.0, 0.0}};
     walk2<T, KMODE, false>(a, dc, col, s0, s1, c, D);
+    const int64_t plane = (int64_t)2 * nr * a.ncols;
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
-        const int64_t o = (((int64_t)dir * a.ncols + col) * nr + r) * 2;
+        const int64_t o = rc_at(a.ncols, nr, dir, r, col);
         rc[o] = c[dir];
-        rc[o + 1] = D[dir];
+        rc[plane + o] = D[dir];
     }
 }
 
-// (2) one work-group of NT threads per column: exclusive scan of the range
-// transfers in the direction of propagation; leaves the carry into each range
-// in rc[.].c (NT = 1024 for long columns keeps each thread's serial part short)
-template <int NT>
-__global__ __launch_bounds__(NT) void k_cscan(int ncols, int nr, cx<double> *rc) {
-    __shared__ cx<double> sc[NT], sd[NT];
-    const int col = blockIdx.x, t = threadIdx.x;
-    const int per = (nr + NT - 1) / NT;
+// (2) one work-group per CPG adjacent columns, TPC threads per column
+// (thread = position * CPG + column, so a wave reads CPG consecutive columns
+// of several ranges at once): exclusive scan of the range transfers in the
+// direction of propagation; leaves the carry into each range in the c plane.
+// Each thread composes a run of ceil(nr / TPC) ranges serially, then the runs
+// are combined by a Hillis-Steele scan in LDS and re-walked.
+template <int CPG, int TPC>
+__global__ __launch_bounds__(CPG *TPC) void k_cscan(int ncols, int nr, cx<double> *rc) {
+    __shared__ cx<double> sc[TPC][CPG], sd[TPC][CPG];
+    const int cl = threadIdx.x % CPG, t = threadIdx.x / CPG;
+    const int col = blockIdx.x * CPG + cl;
+    const bool live = col < ncols;
+    const int per = (nr + TPC - 1) / TPC;
+    const int64_t plane = (int64_t)2 * nr * ncols;
     for (int dir = 0; dir < 2; ++dir) {
-        cx<double> *base = rc + ((int64_t)dir * ncols + col) * nr * 2;
         // thread t owns propagation positions [t*per, (t+1)*per)
-        auto at = [&](int pos) { return dir ? nr - 1 - pos : pos; };
+        auto at = [&](int pos) { return rc_at(ncols, nr, dir, dir ? nr - 1 - pos : pos, col); };
         cx<double> c{0.0, 0.0}, D{1.0, 0.0};
         for (int k = 0; k < per; ++k) {
             const int pos = t * per + k;
-            if (pos < nr) {
-                const int r = at(pos);
-                cx<double> cr = base[2 * r], Dr = base[2 * r + 1];
+            if (live && pos < nr) {
+                const int64_t o = at(pos);
+                cx<double> cr = rc[o], Dr = rc[plane + o];
                 compose(cr, Dr, c, D);
                 c = cr;
                 D = Dr;
             }
         }
-        sc[t] = c;
-        sd[t] = D;
+        sc[t][cl] = c;
+        sd[t][cl] = D;
         __syncthreads();
-        for (int off = 1; off < NT; off <<= 1) {
+        for (int off = 1; off < TPC; off <<= 1) {
             cx<double> pc{0.0, 0.0}, pd{1.0, 0.0};
             const bool has = t >= off;
             if (has) {
-                pc = sc[t - off];
-                pd = sd[t - off];
+                pc = sc[t - off][cl];
+                pd = sd[t - off][cl];
             }
             __syncthreads();
             if (has) compose(c, D, pc, pd);
-            sc[t] = c;
-            sd[t] = D;
+            sc[t][cl] = c;
+            sd[t][cl] = D;
             __syncthreads();
         }
-        cx<double> cin = t > 0 ? sc[t - 1] : cx<double>{0.0, 0.0};
+        cx<double> cin = t > 0 ? sc[t - 1][cl] : cx<double>{0.0, 0.0};
         __syncthreads();
         for (int k = 0; k < per; ++k) {
             const int pos = t * per + k;
-            if (pos < nr) {
-                const int r = at(pos);
-                const cx<double> cr = base[2 * r], Dr = base[2 * r + 1];
-                base[2 * r] = cin;
+            if (live && pos < nr) {
+                const int64_t o = at(pos);
+                const cx<double> cr = rc[o], Dr = rc[plane + o];
+                rc[o] = cin;
                 cx<double> nc = cr, nD = Dr;
                 compose(nc, nD, cin, cx<double>{0.0, 0.0});
                 cin = nc;
@@ -1030,7 +1043,7 @@ __global__ __launch_bounds__(256) void k_capply(const CArgs<T> a, int nr, const 
     const Decay<T, KMODE> dc(a, col);
     cx<double> c[2], D[2] = {{1.0, 0.0}, {1.0, 0.0}};
 #pragma unroll
-    for (int dir = 0; dir < 2; ++dir) c[dir] = rc[(((int64_t)dir * a.ncols + col) * nr + r) * 2];
+    for (int dir = 0; dir < 2; ++dir) c[dir] = rc[rc_at(a.ncols, nr, dir, r, col)];
     walk2<T, KMODE, true>(a, dc, col, s0, s1, c, D);
 }
 
@@ -1043,12 +1056,15 @@ q2d_status carry_run(Plan *p, const CArgs<T> &ca, Buf &tmp) {
     const int64_t nt = (int64_t)ca.ncols * nr;
     const int nb = (int)((nt + 255) / 256);
     k_cfold<T, KMODE><<<nb, 256, 0, p->stream>>>(ca, nr, rc);
-    // (1024-thread work-groups wait for a nearly idle CU while other passes
-    // run concurrently: only for very long columns)
-    if (nr > 4096)
-        k_cscan<1024><<<ca.ncols, 1024, 0, p->stream>>>(ca.ncols, nr, rc);
+    // short columns: 8 columns of 32 threads per work-group; long ones: one
+    // column per work-group (1024-thread work-groups wait for a nearly idle CU
+    // while other passes run concurrently: only for very long columns)
+    if (nr <= 256)
+        k_cscan<8, 32><<<(ca.ncols + 7) / 8, 256, 0, p->stream>>>(ca.ncols, nr, rc);
+    else if (nr <= 4096)
+        k_cscan<1, 256><<<ca.ncols, 256, 0, p->stream>>>(ca.ncols, nr, rc);
     else
-        k_cscan<256><<<ca.ncols, 256, 0, p->stream>>>(ca.ncols, nr, rc);
+        k_cscan<1, 1024><<<ca.ncols, 1024, 0, p->stream>>>(ca.ncols, nr, rc);
     k_capply<T, KMODE><<<nb, 256, 0, p->stream>>>(ca, nr, rc);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
