@@ -153,6 +153,10 @@ struct KArgs {
     int nmodes, gpad;
     int nunits;
     Unit units[MAX_UNITS];
+    // sweep: 1 if each direction runs in its own work-group (block 2 b + d
+    // sweeps unit block b in direction d); the backward outputs then go to
+    // chunk + bchunk
+    int split, bchunk;
     // replica batches: replica of each segment, and the distance between two
     // replicas' mode and coefficient tables (null / 0 for one system)
     const int32_t *seg_rep;
@@ -182,14 +186,14 @@ struct LaneMap {
 };
 
 template <typename T>
-__device__ inline LaneMap lane_map(const KArgs<T> &a) {
+__device__ inline LaneMap lane_map(const KArgs<T> &a, int bx) {
     LaneMap r;
     int k = 0;
     for (int t = 1; t < a.nunits; ++t)
-        if ((int)blockIdx.x >= a.units[t].b0) k = t;
+        if (bx >= a.units[t].b0) k = t;
     r.u = a.units[k];
     r.wb = WAVE / r.u.F;
-    r.wave = (int)blockIdx.x - r.u.b0;
+    r.wave = bx - r.u.b0;
     const int lane = threadIdx.x;
     r.f = lane / r.wb;
     r.mi = lane % r.wb;
@@ -209,7 +213,7 @@ template <typename T, int MH>
 __global__ __launch_bounds__(64) void k_agg(const KArgs<T> a) {
     using U = typename Tr<T>::U;
     const int lane = threadIdx.x;
-    const LaneMap lm = lane_map(a);
+    const LaneMap lm = lane_map(a, (int)blockIdx.x);
     const int BS = lm.wb;  // steps per block; lane loads segment f = lane / BS, step lane % BS
     __shared__ U c_ux[WAVE], c_uy[WAVE];
     __shared__ T c_q[WAVE], c_zf[WAVE], c_zb[WAVE];
@@ -768,12 +772,15 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
 template <typename T, int MH>
 __global__ __launch_bounds__(64) void k_sweep(const KArgs<T> a) {
     using U = typename Tr<T>::U;
-    const LaneMap lm = lane_map(a);
+    // dir: 0 or 1 for a one-direction work-group, -1 for both
+    const int dir = a.split ? (int)(blockIdx.x & 1) : -1;
+    const LaneMap lm = lane_map(a, a.split ? (int)(blockIdx.x >> 1) : (int)blockIdx.x);
     __shared__ U c_ux[WAVE], c_uy[WAVE];
     __shared__ T c_q[WAVE], c_dz[WAVE];
     __shared__ cx<T> c_d[MH][WAVE];
     __shared__ T red[SUB][4][WAVE + 1];
-    T *outc = a.outk + (int64_t)lm.u.chunk * a.N * 4;
+    // output chunk of this work-group (a backward-only one writes chunk + bchunk)
+    T *outc = a.outk + (int64_t)(lm.u.chunk + (dir == 1 ? a.bchunk : 0)) * a.N * 4;
     const int ng = (lm.u.nm + lm.wb - 1) / lm.wb;
     for (int g = 0; g < ng; ++g) {
         const int ml = g * lm.wb + lm.mi;
@@ -800,9 +807,15 @@ __global__ __launch_bounds__(64) void k_sweep(const KArgs<T> a) {
         }
         // lanes of a padded mode read column m of the aggregates if m < gpad
         // (finite) and carry zero coefficients: their outputs vanish
-        sweep_dir<T, MH, 0>(a, lm, m, mx, my, cf, c_ux, c_uy, c_q, c_dz, c_d, red, outc,
-                            g == 0 && !lm.u.acc);
-        sweep_dir<T, MH, 1>(a, lm, m, mx, my, cf, c_ux, c_uy, c_q, c_dz, c_d, red, outc, false);
+        // the first group of a unit stores its chunk (unless an earlier mode
+        // batch wrote it), later groups add; with both directions in one
+        // work-group the backward pass adds to what the forward pass stored
+        const bool first = g == 0 && !lm.u.acc;
+        if (dir != 1)
+            sweep_dir<T, MH, 0>(a, lm, m, mx, my, cf, c_ux, c_uy, c_q, c_dz, c_d, red, outc, first);
+        if (dir != 0)
+            sweep_dir<T, MH, 1>(a, lm, m, mx, my, cf, c_ux, c_uy, c_q, c_dz, c_d, red, outc,
+                                dir == 1 && first);
     }
 }
 
@@ -1215,13 +1228,18 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         gpc = (ngroups0 + MAX_UNITS - nbands - 1) / (MAX_UNITS - nbands);
     const int nch_full = ngroups0 > 0 ? (ngroups0 + gpc - 1) / gpc : 0;
     const int nchunks = nch_full + nbands;
+    // one work-group per direction: twice the waves at half the length, so
+    // the last round of the grid and the slow narrow bands leave a shorter
+    // tail (Q2D_SPLIT=0: both directions in one work-group)
+    const bool split = env_int("Q2D_SPLIT", 1) != 0;
+    const int nout = split ? 2 * nchunks : nchunks;
     const int64_t gpad_max = std::min(nfull, MB) + rem;
     q2d_status st;
     if ((st = ensure(p, p->spans, (size_t)nseg * mh * 2 * sizeof(cx<double>))) != Q2D_OK) return st;
     if ((st = ensure(p, p->agg, (size_t)2 * nseg * (mh + 1) * 2 * gpad_max * sizeof(cx<T>))) !=
         Q2D_OK)
         return st;
-    if ((st = ensure(p, p->outk, (size_t)nchunks * N * 4 * sizeof(T))) != Q2D_OK) return st;
+    if ((st = ensure(p, p->outk, (size_t)nout * N * 4 * sizeof(T))) != Q2D_OK) return st;
     if (!agg_fills_spans<T>(p)) {
         const int64_t n = (int64_t)nseg * mh;
         k_spans<T><<<(int)((n + 255) / 256), 256, 0, p->stream>>>((const T *)p->s_z.p, N, S, nseg,
@@ -1248,17 +1266,20 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
     ka.seg_rep = seg_rep;
     ka.rep_mstride = p->R ? p->rep_mstride : 0;
     ka.rep_cstride = p->R ? p->rep_cstride : 0;
+    ka.split = split ? 1 : 0;
+    ka.bchunk = split ? nchunks : 0;
     for (int bi = 0; bi < nbatch; ++bi) {
         const int64_t b0 = (int64_t)bi * MB;
         const int nbf = (int)std::max<int64_t>(0, std::min(MB, nfull - b0));
         const bool last = bi == nbatch - 1;
         const int ngroups = nbf / WAVE;
-        // bands first: their waves are the slowest per step, dispatched
-        // early they do not form the tail
+        // bands first, the narrowest first: their waves are the slowest per
+        // step (a staging round every 64 / F steps), dispatched early they do
+        // not form the tail
         int nu = 0, blocks = 0, nbm = nbf;
         if (last) {
             int band = 0, left = rem;
-            for (int w = WAVE / 2; w >= SUB; w >>= 1)
+            for (int w = SUB; w <= WAVE / 2; w <<= 1)
                 if (rem4 & w) {
                     const int F = WAVE / w, nm = std::min(w, left);
                     ka.units[nu++] = Unit{F, nbm, nm, nch_full + band, blocks, 0};
@@ -1299,10 +1320,10 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
         ca.rep_cstride = ka.rep_cstride;
         if ((st = carry_run<T, true>(p, ca, p->carry_tmp)) != Q2D_OK) return st;
         tstart(p, 0);
-        dispatch_sweep<T>(p, ka, dim3(blocks));
+        dispatch_sweep<T>(p, ka, dim3(split ? 2 * blocks : blocks));
         tstop(p, 0);
     }
-    *nchunks_out = nchunks;
+    *nchunks_out = nout;
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
