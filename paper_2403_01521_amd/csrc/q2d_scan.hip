@@ -1069,10 +1069,11 @@ q2d_status carry_run(Plan *p, const CArgs<T> &ca, Buf &tmp) {
     const int64_t nt = (int64_t)ca.ncols * nr;
     const int nb = (int)((nt + 255) / 256);
     k_cfold<T, KMODE><<<nb, 256, 0, p->stream>>>(ca, nr, rc);
-    // short columns: 8 columns of 32 threads per work-group; long ones: one
-    // column per work-group (1024-thread work-groups wait for a nearly idle CU
-    // while other passes run concurrently: only for very long columns)
-    if (nr <= 256)
+    // many columns of up to 2048 ranges: 8 columns of 32 threads per
+    // work-group; few columns (the k = 0 carries): one column per work-group
+    // (1024-thread work-groups wait for a nearly idle CU while other passes
+    // run concurrently: only for very long columns)
+    if (ca.ncols >= 256 ? nr <= 2048 : nr <= 256)
         k_cscan<8, 32><<<(ca.ncols + 7) / 8, 256, 0, p->stream>>>(ca.ncols, nr, rc);
     else if (nr <= 4096)
         k_cscan<1, 256><<<ca.ncols, 256, 0, p->stream>>>(ca.ncols, nr, rc);
