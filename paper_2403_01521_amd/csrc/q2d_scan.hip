@@ -110,6 +110,13 @@ __device__ inline cx<double> span_decay(double br, double bi, double t) {
 }
 __device__ inline float expm_real(float k, float t) { return __expf(-k * t); }
 __device__ inline double expm_real(double k, double t) { return exp(-k * t); }
+// e^{-k t} from a coefficient scaled once: FP32 keeps kl = -k log2(e) and
+// takes one hardware exp2 per use (one multiply fewer than e^{-k t}); FP64
+// keeps kl = -k
+__device__ inline float kpre(float k) { return -k * 1.4426950408889634f; }
+__device__ inline double kpre(double k) { return -k; }
+__device__ inline float exp_pre(float kl, float t) { return __builtin_amdgcn_exp2f(kl * t); }
+__device__ inline double exp_pre(double kl, double t) { return exp(kl * t); }
 
 // lane exchange inside groups of four lanes (DPP quad permutations)
 __device__ inline float quad_xor1(float v) {
@@ -440,7 +447,7 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
             const bool mv = m < a.nmodes;
             pmx[cc] = mv ? a.modes[mb + a.moff + m] : 0;
             pmy[cc] = mv ? a.modes[mb + a.mstride + a.moff + m] : 0;
-            pk[cc] = mv ? a.coef[cb + 2 * a.cstride + a.moff + m] : 0.f;
+            pk[cc] = mv ? kpre(a.coef[cb + 2 * a.cstride + a.moff + m]) : 0.f;
         }
         f4v acc[2 * CPW][NCT];
 #pragma unroll
@@ -510,8 +517,8 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
                         const float qv = L.q[e0 + e];
                         xs[e] = qv * cs;
                         ys[e] = qv * sn;
-                        const float ef = __expf(-pk[cc] * L.zf[e0 + e]);
-                        const float eb = __expf(-pk[cc] * L.zb[e0 + e]);
+                        const float ef = exp_pre(pk[cc], L.zf[e0 + e]);
+                        const float eb = exp_pre(pk[cc], L.zb[e0 + e]);
                         fk[cc][0] = fma(xs[e], ef, fk[cc][0]);
                         fk[cc][1] = fma(ys[e], ef, fk[cc][1]);
                         fk[cc][2] = fma(xs[e], eb, fk[cc][2]);
@@ -590,7 +597,7 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
 // sweep negates ad, since T - B enters the derivative).
 template <typename T, int MH>
 struct SweepCoef {
-    T kx, ky, k, ak, akd;
+    T kx, ky, k, ak, akd;  // k: the mode's |k| as kpre() scales it
     T alr[MH], ali[MH], adr[MH], adi[MH];
 };
 
@@ -656,7 +663,7 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
                 phase_sc(mx, my, c_ux[ci], c_uy[ci], s, c);
                 const T qj = c_q[ci];
                 const T x = qj * c, y = qj * s;
-                const T dk = expm_real(cf.k, c_dz[ci]);
+                const T dk = exp_pre(cf.k, c_dz[ci]);
                 // explicit FMA chains: X += Re(a T) is two FMAs, not mul+fma+add
                 T X, Y, Xd, Yd;
                 if (DIR == 0) {
@@ -795,7 +802,7 @@ __global__ __launch_bounds__(64) void k_sweep(const KArgs<T> a) {
         SweepCoef<T, MH> cf;
         cf.kx = ld(0);
         cf.ky = ld(1);
-        cf.k = ld(2);
+        cf.k = kpre(ld(2));
         cf.ak = om * ld(4);
         cf.akd = -om * ld(5);
 #pragma unroll
