@@ -57,30 +57,9 @@ __global__ __launch_bounds__(EPI_THREADS) void k_epi(int64_t N, int nchunks, T *
     if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
 }
 
-// input order: particle o takes the combined result of its sorted slot inv[o]
-template <typename T>
-__global__ __launch_bounds__(EPI_THREADS) void k_unsort(int64_t N, const T *__restrict__ res,
-                                                        const int32_t *__restrict__ inv,
-                                                        T *__restrict__ phi, T *__restrict__ F) {
-    const int64_t o = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
-    if (o >= N) return;
-    const T *r = res + (int64_t)inv[o] * 4;
-    if (phi) phi[o] = r[0];
-    if (F) {
-        F[3 * o] = r[1];
-        F[3 * o + 1] = r[2];
-        F[3 * o + 2] = r[3];
-    }
-}
-
-__global__ __launch_bounds__(EPI_THREADS) void k_inv(const int32_t *__restrict__ perm, int64_t N,
-                                                     int32_t *__restrict__ inv) {
-    const int64_t i = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
-    if (i < N) inv[perm[i]] = (int32_t)i;
-}
-
-__global__ __launch_bounds__(EPI_THREADS) void k_energy(const double *__restrict__ epart,
-                                                        int nparts, double *__restrict__ E) {
+// E = 1/2 sum of the block partials, by one whole work-group in a fixed order
+__device__ inline void energy_block(const double *__restrict__ epart, int nparts,
+                                    double *__restrict__ E) {
     __shared__ double red[EPI_THREADS];
     double s = 0.0;
     for (int b = threadIdx.x; b < nparts; b += EPI_THREADS) s += epart[b];
@@ -91,6 +70,39 @@ __global__ __launch_bounds__(EPI_THREADS) void k_energy(const double *__restrict
         __syncthreads();
     }
     if (threadIdx.x == 0) E[0] = 0.5 * red[0];
+}
+
+// input order: particle o takes the combined result of its sorted slot inv[o];
+// work-group 0 also reduces the energy (k_epi's partials are complete when
+// this launch starts), which saves a launch
+template <typename T>
+__global__ __launch_bounds__(EPI_THREADS) void k_unsort(int64_t N, const T *__restrict__ res,
+                                                        const int32_t *__restrict__ inv,
+                                                        T *__restrict__ phi, T *__restrict__ F,
+                                                        const double *__restrict__ epart,
+                                                        int nparts, double *__restrict__ E) {
+    const int64_t o = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
+    if (o < N) {
+        const T *r = res + (int64_t)inv[o] * 4;
+        if (phi) phi[o] = r[0];
+        if (F) {
+            F[3 * o] = r[1];
+            F[3 * o + 1] = r[2];
+            F[3 * o + 2] = r[3];
+        }
+    }
+    if (E && blockIdx.x == 0) energy_block(epart, nparts, E);
+}
+
+__global__ __launch_bounds__(EPI_THREADS) void k_inv(const int32_t *__restrict__ perm, int64_t N,
+                                                     int32_t *__restrict__ inv) {
+    const int64_t i = (int64_t)blockIdx.x * EPI_THREADS + threadIdx.x;
+    if (i < N) inv[perm[i]] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(EPI_THREADS) void k_energy(const double *__restrict__ epart,
+                                                        int nparts, double *__restrict__ E) {
+    energy_block(epart, nparts, E);
 }
 
 __global__ void k_set_zero(double *E) { E[0] = 0.0; }
@@ -185,16 +197,18 @@ q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0,
         k_epi<double><<<nb, EPI_THREADS, 0, p->stream>>>(N, n_chunks, (double *)p->outk.p,
                                                          (const double *)p->s_q.p, phi0, fz0,
                                                          diag, self_c, (double *)p->epart.p);
+    const double *ep = (const double *)p->epart.p;
     if (out) {
         const int32_t *inv = (const int32_t *)p->inv.p;
         if (p->fp32)
             k_unsort<float><<<nb, EPI_THREADS, 0, p->stream>>>(N, (const float *)p->outk.p, inv,
-                                                               (float *)phi, (float *)F);
+                                                               (float *)phi, (float *)F, ep, nb, E);
         else
-            k_unsort<double><<<nb, EPI_THREADS, 0, p->stream>>>(N, (const double *)p->outk.p, inv,
-                                                                (double *)phi, (double *)F);
+            k_unsort<double><<<nb, EPI_THREADS, 0, p->stream>>>(
+                N, (const double *)p->outk.p, inv, (double *)phi, (double *)F, ep, nb, E);
+    } else if (E) {
+        k_energy<<<1, EPI_THREADS, 0, p->stream>>>(ep, nb, E);
     }
-    if (E) k_energy<<<1, EPI_THREADS, 0, p->stream>>>((const double *)p->epart.p, nb, E);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
