@@ -623,6 +623,7 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
         pky = a.agg[agg_idx<MH>(a.nseg, a.gpad, DIR, lm.seg, MH, 1, m)].re;
     }
     const int js = lane % BS, wi = js * F + lm.f;  // step-major LDS entries
+    const int lbs = __builtin_ctz(BS);             // BS = 64 / F, a power of two
     const int nblk = a.S / BS;                     // S is a multiple of 64
     // reduction geometry: lane reads 16 entries of row (lane >> 2)
     const int rrow = lane >> 2, rchunk = lane & 3;
@@ -740,34 +741,32 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
                 const int pj = r0 + rr;
                 const int jp = DIR ? BS - 1 - pj : pj;
                 const int loc = blk * BS + jp;
+                // add a segment group's sum to its output element (BS is a
+                // power of two: shifts, not divisions, pick the group)
+                auto put = [&](int g, T sum) {
+                    const int sf = lm.wave * F + g;
+                    if (sf < a.nseg) {
+                        const int64_t base = (int64_t)sf * a.S;
+                        const int nf = (int)min((int64_t)a.S, a.N - base);
+                        if (loc < nf) {
+                            T *o = outc + (base + loc) * 4 + rv;
+                            *o = store ? sum : *o + sum;
+                        }
+                    }
+                };
                 if (BS >= 16) {
                     T sum = 0;
 #pragma unroll
                     for (int L = 0; L < 16; ++L) sum += red[rr][rv][c0 + L];
                     if (BS >= 32) sum += quad_xor1(sum);
                     if (BS >= 64) sum += quad_xor2(sum);
-                    if (c0 % BS == 0) {
-                        const int sf = lm.wave * F + c0 / BS;
-                        const int nf = sf < a.nseg ? (int)(min((int64_t)(sf + 1) * a.S, a.N) -
-                                                            (int64_t)sf * a.S)
-                                                   : 0;
-                        if (loc < nf) {
-                            T *o = outc + ((int64_t)sf * a.S + loc) * 4 + rv;
-                            *o = store ? sum : *o + sum;
-                        }
-                    }
+                    if ((c0 & (BS - 1)) == 0) put(c0 >> lbs, sum);
                 } else {
-                    for (int t = 0; t < 16 / BS; ++t) {
+                    // BS = 8 or 4: the 16 entries hold 2 or 4 segment groups
+                    for (int t = 0; t < (16 >> lbs); ++t) {
                         T sum = 0;
-                        for (int L = 0; L < BS; ++L) sum += red[rr][rv][c0 + t * BS + L];
-                        const int sf = lm.wave * F + (c0 + t * BS) / BS;
-                        const int nf = sf < a.nseg ? (int)(min((int64_t)(sf + 1) * a.S, a.N) -
-                                                            (int64_t)sf * a.S)
-                                                   : 0;
-                        if (loc < nf) {
-                            T *o = outc + ((int64_t)sf * a.S + loc) * 4 + rv;
-                            *o = store ? sum : *o + sum;
-                        }
+                        for (int L = 0; L < BS; ++L) sum += red[rr][rv][c0 + (t << lbs) + L];
+                        put((c0 >> lbs) + t, sum);
                     }
                 }
             }
