@@ -845,7 +845,8 @@ struct CArgs {
 };
 
 constexpr int CAR_L = 8;       // segments per range
-constexpr int CAR_BATCH = 4;   // loads issued ahead of the dependent chain
+constexpr int CAR_BATCH = 2;   // loads issued ahead of the dependent chain (2: 103-110
+                               // VGPRs, 4 waves per SIMD; 4 and 8 took 3 and 2 and were slower)
 
 // Compose two range transfers x -> c + D x: first (c1, D1), then (c2, D2).
 __device__ inline void compose(cx<double> &c2, cx<double> &D2, cx<double> c1, cx<double> D1) {
