@@ -19,7 +19,9 @@
 //    computed once per 64-particle block into LDS and read as broadcasts;
 //  * the particle axis is cut into segments of S consecutive sorted
 //    particles; a wave sweeps one segment sequentially (the recursion) for
-//    its modes, after (1) an aggregate pass gives every segment's total
+//    its modes in one direction (the forward and backward sweeps start from
+//    their own carries, so they run in separate work-groups), after (1) an
+//    aggregate pass gives every segment's total
 //    contribution referenced to its end (forward) and start (backward), and
 //    (2) an FP64 scan over segments turns aggregates into carry-ins.  Every
 //    cross-segment factor is one exponential of a z difference, never a long
@@ -732,10 +734,11 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
             // per step and segment group: the sum of 4 outputs over its wb
             // lanes (rows padded to 65 entries: conflict-free); a lane sums
             // 16 consecutive entries of one row, then partial sums of a group
-            // wider than 16 lanes are combined by quad exchanges.  The unit's
-            // output chunk receives it: stored by the forward sweep of its
-            // first group (store), added otherwise; every element has one
-            // writer per pass and passes are separated by barriers.
+            // wider than 16 lanes are combined by quad exchanges.  The output
+            // chunk of the unit (and direction) receives it: stored by the
+            // first pass that writes the chunk (store), added by later ones;
+            // every element has one writer per pass and passes are separated
+            // by barriers.
             __syncthreads();
             {
                 const int pj = r0 + rr;
@@ -1203,7 +1206,9 @@ int choose_S(int64_t N) {
 // each a band unit with F = 64 / w segments per wave, so every lane holds a
 // mode (up to 3 padded lanes in the last band) and every wave sweeps S
 // particles.  Mode tables longer than MB run in batches; bands join the last.
-// Output chunks: one per unit (batches add into the F = 1 ones).
+// Output chunks: one per unit and direction when each direction has its own
+// work-groups (the default), else one per unit; later mode batches add into
+// the F = 1 units' chunks.
 template <typename T>
 q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coef,
                        int64_t cstride, int64_t moff0, int64_t nmodes, int *nchunks_out) {
