@@ -633,7 +633,10 @@ __device__ inline void sweep_dir(const KArgs<T> &a, const LaneMap &lm, int m, in
     const int c0 = rchunk * 16;
     for (int bb = 0; bb < nblk; ++bb) {
         const int blk = DIR ? (nblk - 1 - bb) : bb;
-        __syncthreads();
+        // after the first block, the barrier that ends the previous block's
+        // last round already orders its reads before this staging (one
+        // barrier per block fewer: narrow bands stage every 64 / F steps)
+        if (bb == 0) __syncthreads();
         {
             // positions past the segment's end hold a zero source and a unit
             // decay: the recursion passes them through unchanged and their
