@@ -210,6 +210,12 @@ q2d_status q2d_soe_fit(int32_t M, double *w, double *s, double *sup_err);
  */
 q2d_status q2d_plan_timing_enable(q2d_plan_t plan, int32_t mask);
 q2d_status q2d_plan_timing_read(q2d_plan_t plan, int32_t which, double *ms_total, int64_t *count);
+/*
+ * Record the selected families only on every n-th call of the plan's entry
+ * points (n >= 1; 1, the default, records every call), so that a timed loop
+ * carries fewer events.  Returns Q2D_EINVAL for n < 1.
+ */
+q2d_status q2d_plan_timing_stride(q2d_plan_t plan, int32_t n);
 
 /*
  * Replica batches -- R independent systems advanced by one random-batch step

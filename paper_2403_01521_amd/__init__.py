@@ -39,6 +39,7 @@ EXPORTS = ("q2d_plan_create", "q2d_plan_destroy", "q2d_plan_set_stream", "q2d_pl
            "q2d_batch_check",
            "q2d_plan_check",
            "q2d_soe_fit", "q2d_plan_timing_enable", "q2d_plan_timing_read",
+           "q2d_plan_timing_stride",
            "q2d_status_string")
 
 
@@ -90,6 +91,7 @@ def load_library(path=None):
     lib.q2d_soe_fit.argtypes = [i32, dp, dp, dp]
     lib.q2d_plan_timing_enable.argtypes = [vp, i32]
     lib.q2d_plan_timing_read.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.q2d_plan_timing_stride.argtypes = [vp, i32]
     i64p = ctypes.POINTER(ctypes.c_int64)
     i32p = ctypes.POINTER(ctypes.c_int32)
     lib.q2d_batch_create.argtypes = [i32, dp, i64p, dbl, i32, dp, dp, ctypes.POINTER(_Opts), vp,
@@ -296,6 +298,10 @@ class Plan:
         if mask is True:
             mask = TIMING_ALL
         _check(self._lib.q2d_plan_timing_enable(self._h, int(mask)), "timing_enable")
+
+    def timing_stride(self, n):
+        """Record the timed kernel families on every n-th call only (n >= 1)."""
+        _check(self._lib.q2d_plan_timing_stride(self._h, int(n)), "timing_stride")
 
     def timing_read(self, which):
         ms = ctypes.c_double(0.0)

@@ -45,8 +45,15 @@ int env_int(const char *name, int dflt) {
     return (v && *v) ? atoi(v) : dflt;
 }
 
+// calls are counted where every entry point starts its call timer; a call
+// records its events only if it is a sampled one (every timing_stride-th)
+static bool timing_on(const Plan *p, int which) {
+    return (p->timing & (1 << which)) && p->ncalls % p->timing_stride == 0;
+}
+
 void tstart(Plan *p, int which) {
-    if (!(p->timing & (1 << which))) return;
+    if (which == 4) ++p->ncalls;
+    if (!timing_on(p, which)) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     (void)hipEventRecord(e, p->stream);
@@ -54,7 +61,7 @@ void tstart(Plan *p, int which) {
 }
 
 void tstop(Plan *p, int which) {
-    if (!(p->timing & (1 << which))) return;
+    if (!timing_on(p, which)) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     (void)hipEventRecord(e, p->stream);
@@ -743,6 +750,13 @@ q2d_status q2d_plan_timing_enable(q2d_plan_t p, int32_t mask) {
         p->t_cnt[w] = 0;
     }
     p->timing = mask & 31;
+    return Q2D_OK;
+}
+
+q2d_status q2d_plan_timing_stride(q2d_plan_t p, int32_t n) {
+    if (!p || n < 1) return Q2D_EINVAL;
+    p->timing_stride = n;
+    p->ncalls = 0;
     return Q2D_OK;
 }
 

@@ -147,6 +147,8 @@ struct Plan {
 
     // timing
     int timing = 0;  // bit mask of timed kernel families
+    int timing_stride = 1;  // record on every timing_stride-th call only
+    int64_t ncalls = 0;     // entry-point calls (counted at the call timer's start)
     // Q2D_SERIAL=1 at plan creation: the side-stream work runs on the caller's
     // stream (no overlap; for per-kernel profiles)
     bool serial = false;

@@ -164,3 +164,30 @@ def test_deterministic(soe_tables):
     for x, y in zip(a, b):
         assert torch.equal(x, y)
     plan.close()
+
+
+def test_kernel_timers_and_stride(soe_tables):
+    """The measurement hooks: with timers on every call each family records one
+    launch per step (the sweep is one launch per step); with stride n only every
+    n-th call records, and results do not depend on either."""
+    c = wl.make_config(3, dtype=np.float32, n_override=20000)
+    w, s = soe_tables[16]
+    P = 100
+    plan = q2d.Plan(c["box"], c["alpha"], w, s, precision="fp32", n_max=len(c["q"]), p_max=P)
+    pos, q = dev(c["pos"], torch.float32), dev(c["q"], torch.float32)
+    ref = plan.rbm_step(pos, q, P, seed=3, step=1)[1].cpu().numpy()
+    plan.timing_enable(1 << q2d.TIMER_SWEEP | 1 << q2d.TIMER_CALL)
+    for k in range(8):
+        plan.rbm_step(pos, q, P, seed=3, step=1)
+    ms, cnt = plan.timing_read(q2d.TIMER_SWEEP)
+    assert cnt == 8 and ms > 0
+    assert plan.timing_read(q2d.TIMER_CALL)[1] == 8
+    plan.timing_enable(1 << q2d.TIMER_SWEEP)
+    plan.timing_stride(4)
+    for k in range(8):
+        F = plan.rbm_step(pos, q, P, seed=3, step=1)[1]
+    assert plan.timing_read(q2d.TIMER_SWEEP)[1] == 2
+    assert np.array_equal(F.cpu().numpy(), ref)
+    with pytest.raises(q2d.Q2DError):
+        plan.timing_stride(0)
+    plan.close()
