@@ -34,41 +34,60 @@ struct alignas(4 * sizeof(T)) Rec {
     T x, y, z, q;
 };
 
+// One sort tile per work-group (SORT_ITEMS particles per thread, coalesced):
+// keys, identity values and records in input order, plus the tile's
+// histogram of the first digit, so the first sort pass needs no histogram
+// launch of its own.
 template <typename T, typename K>
-__global__ __launch_bounds__(256) void k_stage(const T *__restrict__ pos, const T *__restrict__ q,
-                                               int64_t N, K *__restrict__ keys,
-                                               int32_t *__restrict__ vals, Rec<T> *__restrict__ rec,
-                                               double Lz, int validate, int *status, double *qsums) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double qv = 0.0;
-    if (i < N) {
-        const T z = pos[3 * i + 2];
-        keys[i] = zkey(z);
-        vals[i] = (int32_t)i;
-        rec[i] = Rec<T>{pos[3 * i], pos[3 * i + 1], z, q[i]};
-        if (validate) {
-            const T x = pos[3 * i], y = pos[3 * i + 1];
-            qv = (double)q[i];
-            const bool finite = isfinite((double)x) && isfinite((double)y) &&
-                                isfinite((double)z) && isfinite(qv);
-            if (!finite || !((double)z >= 0.0 && (double)z <= Lz)) set_status(status, Q2D_EOUTOFBOX);
+__global__ __launch_bounds__(SORT_THREADS) void k_stage(
+    const T *__restrict__ pos, const T *__restrict__ q, int64_t N, K *__restrict__ keys,
+    int32_t *__restrict__ vals, Rec<T> *__restrict__ rec, uint32_t *__restrict__ hist, int ntiles,
+    double Lz, int validate, int *status, double *qsums) {
+    __shared__ uint32_t h[256];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    double qs = 0.0, qa = 0.0;
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int64_t i = base + r * SORT_THREADS + t;
+        if (i < N) {
+            const T z = pos[3 * i + 2];
+            const K key = zkey(z);
+            keys[i] = key;
+            vals[i] = (int32_t)i;
+            rec[i] = Rec<T>{pos[3 * i], pos[3 * i + 1], z, q[i]};
+            atomicAdd(&h[(uint32_t)key & 255u], 1u);
+            if (validate) {
+                const T x = pos[3 * i], y = pos[3 * i + 1];
+                const double qv = (double)q[i];
+                qs += qv;
+                qa += fabs(qv);
+                const bool finite = isfinite((double)x) && isfinite((double)y) &&
+                                    isfinite((double)z) && isfinite(qv);
+                if (!finite || !((double)z >= 0.0 && (double)z <= Lz))
+                    set_status(status, Q2D_EOUTOFBOX);
+            }
         }
     }
+    __syncthreads();
+    hist[(int64_t)t * ntiles + blockIdx.x] = h[t];
     if (validate) {
         // block sums of q and |q| for the neutrality check (order of the final
         // atomic adds only affects a threshold test)
-        __shared__ double s1[256], s2[256];
-        s1[threadIdx.x] = qv;
-        s2[threadIdx.x] = fabs(qv);
+        __shared__ double s1[SORT_THREADS], s2[SORT_THREADS];
+        s1[t] = qs;
+        s2[t] = qa;
         __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) {
-                s1[threadIdx.x] += s1[threadIdx.x + h];
-                s2[threadIdx.x] += s2[threadIdx.x + h];
+        for (int hh = SORT_THREADS / 2; hh > 0; hh >>= 1) {
+            if (t < hh) {
+                s1[t] += s1[t + hh];
+                s2[t] += s2[t + hh];
             }
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
+        if (t == 0) {
             atomicAdd(&qsums[0], s1[0]);
             atomicAdd(&qsums[1], s2[0]);
         }
@@ -266,19 +285,20 @@ q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
     double *qsums = (double *)((char *)p->status.p + 16);
     const int nb = (int)((N + 255) / 256);
     if (p->opts.validate) k_zero2<<<1, 1, 0, p->stream>>>(qsums);
-    k_stage<T, K><<<nb, 256, 0, p->stream>>>(pos, q, N, (K *)p->keys_a.p, (int32_t *)p->vals_a.p,
-                                             (Rec<T> *)p->recs.p, p->Lz, p->opts.validate, status,
-                                             qsums);
-    if (p->opts.validate) k_neutral_check<<<1, 1, 0, p->stream>>>(qsums, status);
-
     uint32_t *hist = (uint32_t *)p->hist.p;
     uint32_t *tot = hist + (size_t)256 * ntiles;
+    k_stage<T, K><<<ntiles, SORT_THREADS, 0, p->stream>>>(
+        pos, q, N, (K *)p->keys_a.p, (int32_t *)p->vals_a.p, (Rec<T> *)p->recs.p, hist, ntiles,
+        p->Lz, p->opts.validate, status, qsums);
+    if (p->opts.validate) k_neutral_check<<<1, 1, 0, p->stream>>>(qsums, status);
+
     K *kin = (K *)p->keys_a.p, *kout = (K *)p->keys_b.p;
     int32_t *vin = (int32_t *)p->vals_a.p, *vout = (int32_t *)p->vals_b.p;
     const int passes = (int)sizeof(K);
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
-        k_hist<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, N, shift, hist, ntiles);
+        // (k_stage wrote the first pass's tile histograms)
+        if (pass > 0) k_hist<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, N, shift, hist, ntiles);
         k_scan_digit<<<256, 256, 0, p->stream>>>(hist, ntiles, tot);
         k_scatter<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, vin, kout, vout, N, shift, hist,
                                                             tot, ntiles);
