@@ -147,3 +147,73 @@ def test_rb_estimator_unbiased(soe_tables):
     # and the sample variance matches Prop 4.1 within a loose factor
     assert 0.5 * var1 < np.var(vals) < 2.0 * var1
     assert D > 0
+
+
+def _diag_exact(Lx, Ly, alpha, tol=1e-18):
+    """(pi/A) sum_{k != 0} 2 erfc(k/(2 alpha))/k: the j = i term of phi^k
+    (Sec. 2.2, eq. philk at rho_ij = 0, z_ij = 0, where xi^+ + xi^- = 2 erfc(k/2a)),
+    summed over the whole lattice with the exact (non-SOE) kernel."""
+    from scipy.special import erfc
+    kc = 2 * alpha * np.sqrt(-np.log(tol))
+    m = ewald2d.kmodes_full(Lx, Ly, kc)
+    _, _, k = soewald2d.mode_k(m[:, 0], m[:, 1], Lx, Ly)
+    return np.pi / (Lx * Ly) * float(np.sum(2 * erfc(k / (2 * alpha)) / k)), k
+
+
+@pytest.mark.parametrize("box,alpha", [((20.0, 20.0), 0.4), ((60.0, 35.0), 0.25)])
+@pytest.mark.parametrize("M", [8, 16, 24])
+def test_diag_constant_is_the_j_eq_i_term(soe_tables, box, alpha, M):
+    """The random-batch j = i constant D against the configuration-independent
+    j = i term of U^k summed over k != 0 with the exact kernel (Sec. 3.2: the
+    constant Q pi erfc(k/2a)/(kA) of the rearranged pair sum): their gap must lie
+    within the Thm 3.2 kernel bound summed over the lattice."""
+    w, s = soe_tables[M]
+    eps = _eps(w, s)
+    Lx, Ly = box
+    D = soewald2d.diag_constant(Lx, Ly, alpha, w, s)
+    Dx, k = _diag_exact(Lx, Ly, alpha)
+    g = np.exp(-k * k / (4 * alpha * alpha))
+    # Thm 3.2: |g K_k(0) - (xi^+ + xi^-)(k, 0)/k| <= 2 (2 a g eps / (sqrt(pi) k)) / k
+    bound = np.pi / (Lx * Ly) * float(np.sum(4 * alpha * g * eps / (np.sqrt(np.pi) * k * k)))
+    print("M=%d box=%s: D=%.15e exact=%.15e gap=%.2e bound=%.2e"
+          % (M, box, D, Dx, abs(D - Dx), bound))
+    assert abs(D - Dx) <= 1.01 * bound + 1e-15 * abs(Dx)
+    # the bound is tight enough to see a planted factor: well below |Dx|
+    assert bound < 1e-2 * abs(Dx)
+
+
+def test_diag_constant_equals_pair_sum_difference(soe_tables):
+    """q_i D equals the difference of the direct pair sums (O2) with and without
+    the j = i pair over the whole lattice (k = 0 and self terms left out)."""
+    w, s = soe_tables[16]
+    box = (9.0, 7.0, 3.0)
+    alpha = 0.8
+    pos, q = wl.random_system(6, box, seed=31)
+    q = q * np.array([1.0, 2.0, 1.0, 0.5, 1.0, 1.5])
+    modes, wts = soewald2d.exact_modes(box[0], box[1], alpha, 2 * alpha * np.sqrt(np.log(1e18)))
+    a = soewald2d.long_range(pos, q, box, alpha, w, s, modes, wts, include_self_pair=True, k0=False)
+    b = soewald2d.long_range(pos, q, box, alpha, w, s, modes, wts, include_self_pair=False, k0=False)
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    np.testing.assert_allclose(a["phi"] - b["phi"], q * D, rtol=1e-10, atol=1e-14)
+
+
+def test_diag_constant_pin_catches_planted_mistakes(soe_tables, monkeypatch):
+    """A factor 2 in D, or a wrong Gaussian (e^{-k^2/(4 alpha)}, the printed form
+    of the garbled factor), planted in the oracle, fails the j = i pin."""
+    w, s = soe_tables[16]
+    Lx, Ly, alpha = 20.0, 20.0, 0.4
+    Dx, k = _diag_exact(Lx, Ly, alpha)
+    eps = _eps(w, s)
+    g = np.exp(-k * k / (4 * alpha * alpha))
+    bound = np.pi / (Lx * Ly) * float(np.sum(4 * alpha * g * eps / (np.sqrt(np.pi) * k * k)))
+    D = soewald2d.diag_constant(Lx, Ly, alpha, w, s)
+    assert abs(2 * D - Dx) > 100 * bound
+    real_exp = np.exp
+
+    def wrong_gauss(x, *a, **kw):
+        return real_exp(x * alpha, *a, **kw) if np.ndim(x) == 0 and x < 0 else real_exp(x, *a, **kw)
+
+    monkeypatch.setattr(soewald2d.np, "exp", wrong_gauss)
+    Dw = soewald2d.diag_constant(Lx, Ly, alpha, w, s)
+    monkeypatch.undo()
+    assert abs(Dw - Dx) > 100 * bound
