@@ -25,9 +25,12 @@ Contents (each function cites the passage of the paper it follows):
                     and the normaliser H (Sec. 4.1).
 * ``lattice``    -- brute-force direct lattice sums (Sec. 2.1, Thm 2.1),
                     used to pin O1 on tiny inputs.
+* ``slabs``      -- the particle-slab term of charged walls (Sec. 2.4, Thm 2.7
+                    and eq. spectial) and a BAOAB step of the Langevin
+                    dynamics of Sec. 4.3.
 
 Every function here is plain and slow on purpose.  Parity status of each
 function (what pins it) is listed in the header of its module.
 """
 
-from . import soe, ewald2d, soewald2d, rbsampler, lattice  # noqa: F401
+from . import soe, ewald2d, soewald2d, rbsampler, lattice, slabs  # noqa: F401

@@ -66,23 +66,27 @@ def xi_sum(k, z, alpha):
     return xp + xm, xp - xm
 
 
-def real_space(pos, q, box, alpha, rc):
-    """phi_s and F_s (eq. phi_s): truncated erfc sum over images within rc."""
+def real_space(pos, q, box, alpha, rc, targets=None):
+    """phi_s and F_s (eq. phi_s): truncated erfc sum over images within rc.
+    targets: indices of the particles to evaluate (default all); every
+    particle is a source either way."""
     pos, q = _check(pos, q)
     Lx, Ly, _ = box
-    n = len(q)
+    tg = np.arange(len(q)) if targets is None else np.asarray(targets, dtype=np.int64)
+    n = len(tg)
     phi = np.zeros(n)
     F = np.zeros((n, 3))
     nx = int(np.ceil(rc / Lx)) + 1
     ny = int(np.ceil(rc / Ly)) + 1
-    d0 = pos[:, None, :] - pos[None, :, :]
+    d0 = pos[tg, None, :] - pos[None, :, :]
+    same = tg[:, None] == np.arange(len(q))[None, :]
     for mx in range(-nx, nx + 1):
         for my in range(-ny, ny + 1):
             d = d0 + np.array([mx * Lx, my * Ly, 0.0])
             r = np.sqrt((d * d).sum(-1))
             mask = r <= rc
             if mx == 0 and my == 0:
-                np.fill_diagonal(mask, False)
+                mask &= ~same
             if not mask.any():
                 continue
             rs = np.where(mask, r, 1.0)
@@ -90,21 +94,23 @@ def real_space(pos, q, box, alpha, rc):
             phi += e @ q
             fm = np.where(mask, (erfc(alpha * rs) / rs ** 2
                                  + 2 * alpha / SQRT_PI * np.exp(-(alpha * rs) ** 2) / rs) / rs, 0.0)
-            F += q[:, None] * ((fm * q[None, :])[:, :, None] * d).sum(1)
+            F += q[tg, None] * ((fm * q[None, :])[:, :, None] * d).sum(1)
     return phi, F
 
 
-def fourier_k(pos, q, box, alpha, kc):
-    """sum over 0 < |k| <= kc of phi^k and its force (eq. philk), full lattice."""
+def fourier_k(pos, q, box, alpha, kc, targets=None):
+    """sum over 0 < |k| <= kc of phi^k and its force (eq. philk), full lattice.
+    targets: indices of the particles to evaluate (default all)."""
     pos, q = _check(pos, q)
     Lx, Ly, _ = box
     A = Lx * Ly
-    n = len(q)
+    tg = np.arange(len(q)) if targets is None else np.asarray(targets, dtype=np.int64)
+    n = len(tg)
     phi = np.zeros(n)
     F = np.zeros((n, 3))
-    dx = pos[:, None, 0] - pos[None, :, 0]
-    dy = pos[:, None, 1] - pos[None, :, 1]
-    dz = pos[:, None, 2] - pos[None, :, 2]
+    dx = pos[tg, None, 0] - pos[None, :, 0]
+    dy = pos[tg, None, 1] - pos[None, :, 1]
+    dz = pos[tg, None, 2] - pos[None, :, 2]
     az = np.abs(dz)
     sg = np.sign(dz)
     for mx, my in kmodes_full(Lx, Ly, kc):
@@ -116,25 +122,26 @@ def fourier_k(pos, q, box, alpha, kc):
         s = np.sin(th)
         phi += (np.pi / A) * ((c * G / k) @ q)
         # -d/drho_i cos(k.rho_ij) = k sin(k.rho_ij)
-        fr = (np.pi / A) * q * ((s * G / k) @ q)
+        fr = (np.pi / A) * q[tg] * ((s * G / k) @ q)
         F[:, 0] += kx * fr
         F[:, 1] += ky * fr
         # d/dz_i G(|z_ij|) = sgn(z_ij) k (xi+ - xi-)
-        F[:, 2] += -(np.pi / A) * q * ((c * sg * Gd) @ q)
+        F[:, 2] += -(np.pi / A) * q[tg] * ((c * sg * Gd) @ q)
     return phi, F
 
 
-def fourier_0(pos, q, box, alpha):
-    """phi^0 and its z force (eq. phil0)."""
+def fourier_0(pos, q, box, alpha, targets=None):
+    """phi^0 and its z force (eq. phil0); targets as in fourier_k."""
     pos, q = _check(pos, q)
     Lx, Ly, _ = box
     A = Lx * Ly
-    dz = pos[:, None, 2] - pos[None, :, 2]
+    tg = np.arange(len(q)) if targets is None else np.asarray(targets, dtype=np.int64)
+    dz = pos[tg, None, 2] - pos[None, :, 2]
     az = np.abs(dz)
     K = az * erf(alpha * az) + np.exp(-(alpha * az) ** 2) / (alpha * SQRT_PI)
     phi = -(2 * np.pi / A) * (K @ q)
-    F = np.zeros((len(q), 3))
-    F[:, 2] = (2 * np.pi / A) * q * ((np.sign(dz) * erf(alpha * az)) @ q)
+    F = np.zeros((len(tg), 3))
+    F[:, 2] = (2 * np.pi / A) * q[tg] * ((np.sign(dz) * erf(alpha * az)) @ q)
     return phi, F
 
 
