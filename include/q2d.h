@@ -49,10 +49,23 @@ typedef enum {
     Q2D_ECAPACITY = 5,     /* N > n_max or P > p_max */
     Q2D_EDEVICE = 6,       /* a HIP runtime call failed */
     Q2D_ESAMPLER = 7,      /* the mode sampler found no non-zero proposal */
-    Q2D_EUNSUPPORTED = 8   /* the plan was created without what this call needs */
+    Q2D_EUNSUPPORTED = 8,  /* the plan was created without what this call needs */
+    Q2D_EDTYPE = 9         /* element type of an argument differs from the plan's precision
+                              (reported by bindings that see element types: the C calls
+                              take untyped pointers and read them as the plan's type) */
 } q2d_status;
 
 typedef enum { Q2D_FP64 = 0, Q2D_FP32 = 1 } q2d_precision;
+
+/* Mode samplers of the random batch (Sec. 4.1: modes drawn from
+ * h(k) = exp(-k^2/(4 alpha^2)) / H over k != 0). */
+typedef enum {
+    Q2D_SAMPLER_METROPOLIS = 0,  /* the independence Metropolis chain of App. G */
+    Q2D_SAMPLER_IID = 1          /* exact i.i.d. draws: h factorises over the two axes into
+                                    discrete Gaussians; m_x from its marginal given
+                                    m != (0, 0), then m_y given m_x, each by inversion of a
+                                    cumulative table built in FP64 at plan creation */
+} q2d_sampler;
 
 typedef struct {
     int32_t precision;  /* q2d_precision: element type of pos, q, phi, F and of the scans */
@@ -60,6 +73,7 @@ typedef struct {
     int64_t n_max;      /* largest N any call on this plan will pass (> 0) */
     int32_t p_max;      /* largest batch size P of q2d_rbm_step (0: random batch unused) */
     int32_t validate;   /* nonzero: check neutrality, z in [0, Lz], finiteness on the device */
+    int32_t sampler;    /* q2d_sampler (replica batches: Metropolis only) */
 } q2d_opts;
 
 /* Read-only facts about a plan (host values). */
@@ -181,6 +195,50 @@ q2d_status q2d_short_range(q2d_plan_t plan, const void *pos, const void *q, int6
                            void *F, double *E);
 
 /*
+ * q2d_slab -- particle-slab term of two charged walls at z = 0 and z = Lz
+ * (Sec. 2.4, Thm 2.7; eq. spectial for uniform walls), the p-s part of Alg. 2.
+ * With sb(k), st(k) the Fourier coefficients of one cell of the bottom and top
+ * surface charge densities, sig(k) = integral over [0,Lx) x [0,Ly) of
+ * sigma(rho) e^{-i k.rho}:
+ *   phi_i = (2 pi/A) Re sum_{listed k} e^{i k.rho_i}/k [sb(k) e^{-k|z_i|} + st(k) e^{-k|z_i - Lz|}]
+ *           - (2 pi/A) [sig0_bot |z_i| + sig0_top |z_i - Lz|],
+ * F_i = -q_i grad phi(r_i), E = sum_i q_i phi_i (no 1/2: the walls are
+ * external charges).  Uniform walls of densities sigma_b, sigma_t: n_modes = 0,
+ * sig0_bot = sigma_b A, sig0_top = sigma_t A.  modes: device int32 n_modes x 2
+ * (mx, my), k = 2 pi (mx/Lx, my/Ly), the full lattice list (k and -k both listed
+ * for a real density), no (0, 0); sig_bot, sig_top: device double arrays of
+ * n_modes complex values (re, im interleaved).  Charge neutrality then reads
+ * sum q + sig0_bot + sig0_top = 0 (eq. chargeneu), which the long-range entry
+ * points do not check when walls carry charge (leave opts.validate off).
+ * pos, q: device inputs; phi, F, E: device outputs or NULL.  FP64 arithmetic
+ * for both precisions.
+ */
+q2d_status q2d_slab(q2d_plan_t plan, const void *pos, const void *q, int64_t N, int32_t n_modes,
+                    const int32_t *modes, const double *sig_bot, const double *sig_top,
+                    double sig0_bot, double sig0_top, void *phi, void *F, double *E);
+
+/*
+ * q2d_langevin_step -- one step of the Langevin dynamics of Sec. 4.3
+ * (eq. langevin: dr = p/m dt, dp = (F - gamma p/m) dt + sqrt(2 gamma kT) dW)
+ * by the BAOAB splitting, in two calls around the force evaluation:
+ *   stage 0: p += dt/2 F; r += dt/2 p/m; p = e^{-gamma dt/m} p
+ *            + sqrt(m kT (1 - e^{-2 gamma dt/m})) xi; r += dt/2 p/m; then x, y
+ *            wrap into [0, L) and z folds into [0, Lz] by specular reflection
+ *            at the walls (p_z flips at each reflection);
+ *   stage 1: p += dt/2 F with the forces at the new positions.
+ * F = F0 + F1 + F2 (device N x 3 arrays of the plan's type; NULL ones are
+ * skipped), e.g. the long-range, short-range and particle-slab forces.
+ * pos (stage 0 only), mom: device N x 3, updated in place; mass: device N or
+ * NULL (all 1).  xi: standard normals from Philox4x32-10 with key = seed and
+ * counter (particle, step, stream 3 for x, y; stream 4 for z), Box-Muller;
+ * the same (seed, step) gives the same noise.  dt > 0, gamma >= 0, kT >= 0.
+ */
+q2d_status q2d_langevin_step(q2d_plan_t plan, void *pos, void *mom, const void *mass, int64_t N,
+                             const void *F0, const void *F1, const void *F2, double dt,
+                             double gamma, double kT, uint64_t seed, uint64_t step,
+                             int32_t stage);
+
+/*
  * q2d_plan_check -- wait for the plan's stream and return the first data error
  * found by the device-side checks of the calls since the last check
  * (Q2D_ENONNEUTRAL, Q2D_EOUTOFBOX, Q2D_ESAMPLER) or Q2D_OK; clears it.
@@ -196,6 +254,18 @@ q2d_status q2d_plan_check(q2d_plan_t plan);
  * max |exp(-x^2) - SOE(x)| measured on a grid of [0, 200].
  */
 q2d_status q2d_soe_fit(int32_t M, double *w, double *s, double *sup_err);
+
+/*
+ * q2d_soe_fit_eps -- the same fit with the fewest terms that reaches a
+ * prescribed accuracy (Sec. 3: the SOE error eps of eq. SOE1 is the accuracy
+ * parameter; Sec. 4.3: M is picked for a tolerance): M = 2, 4, ..., M_max is
+ * tried in turn and the first with sup error <= eps is returned in *M, w, s
+ * (host arrays of at least 2 M_max doubles) and *sup_err (may be NULL).
+ * Q2D_ECAPACITY if no M <= M_max reaches eps (w, s, *M then hold the M_max
+ * fit); Q2D_EINVAL for eps <= 0 or M_max outside [2, 64].
+ */
+q2d_status q2d_soe_fit_eps(double eps, int32_t M_max, int32_t *M, double *w, double *s,
+                           double *sup_err);
 
 /*
  * Kernel timing (measurement only): the plan records HIP events around the

@@ -26,7 +26,11 @@ LIB_PATH = os.path.join(_HERE, "libq2d.so")
 STATUS = {
     0: "Q2D_OK", 1: "Q2D_EINVAL", 2: "Q2D_ENONNEUTRAL", 3: "Q2D_EOUTOFBOX", 4: "Q2D_ENOMEM",
     5: "Q2D_ECAPACITY", 6: "Q2D_EDEVICE", 7: "Q2D_ESAMPLER", 8: "Q2D_EUNSUPPORTED",
+    9: "Q2D_EDTYPE",
 }
+Q2D_EINVAL, Q2D_ENONNEUTRAL, Q2D_EOUTOFBOX, Q2D_ECAPACITY, Q2D_EUNSUPPORTED, Q2D_EDTYPE = (
+    1, 2, 3, 5, 8, 9)
+SAMPLERS = {"metropolis": 0, "iid": 1}
 FP64, FP32 = 0, 1
 TIMER_SWEEP, TIMER_AGG, TIMER_SORT, TIMER_K0, TIMER_CALL = 0, 1, 2, 3, 4
 TIMING_ALL = 31
@@ -38,7 +42,9 @@ EXPORTS = ("q2d_plan_create", "q2d_plan_destroy", "q2d_plan_set_stream", "q2d_pl
            "q2d_batch_rbm_step", "q2d_batch_tune", "q2d_batch_capture", "q2d_batch_replay",
            "q2d_batch_check",
            "q2d_plan_check",
-           "q2d_soe_fit", "q2d_plan_timing_enable", "q2d_plan_timing_read",
+           "q2d_slab", "q2d_langevin_step",
+           "q2d_soe_fit", "q2d_soe_fit_eps",
+           "q2d_plan_timing_enable", "q2d_plan_timing_read",
            "q2d_plan_timing_stride",
            "q2d_status_string")
 
@@ -52,7 +58,7 @@ class Q2DError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("thin", ctypes.c_int32),
                 ("n_max", ctypes.c_int64), ("p_max", ctypes.c_int32),
-                ("validate", ctypes.c_int32)]
+                ("validate", ctypes.c_int32), ("sampler", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -88,7 +94,11 @@ def load_library(path=None):
     lib.q2d_modes_eval.argtypes = [vp, vp, vp, i64, vp, vp, i64, vp, vp, vp]
     lib.q2d_short_range.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     lib.q2d_plan_check.argtypes = [vp]
+    lib.q2d_slab.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp, dbl, dbl, vp, vp, vp]
+    lib.q2d_langevin_step.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, dbl, dbl, dbl, u64, u64,
+                                      i32]
     lib.q2d_soe_fit.argtypes = [i32, dp, dp, dp]
+    lib.q2d_soe_fit_eps.argtypes = [dbl, i32, ctypes.POINTER(ctypes.c_int32), dp, dp, dp]
     lib.q2d_plan_timing_enable.argtypes = [vp, i32]
     lib.q2d_plan_timing_read.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.q2d_plan_timing_stride.argtypes = [vp, i32]
@@ -138,6 +148,21 @@ def soe_fit(M):
     return w[0::2] + 1j * w[1::2], s[0::2] + 1j * s[1::2], err.value
 
 
+def soe_fit_eps(eps, M_max=64):
+    """Fewest-term host SOE with sup error <= eps: (w, s, M, sup_err); raises
+    Q2DError(Q2D_ECAPACITY) if M_max terms do not reach eps."""
+    lib = load_library()
+    w = np.zeros(2 * M_max)
+    s = np.zeros(2 * M_max)
+    M = ctypes.c_int32(0)
+    err = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.q2d_soe_fit_eps(float(eps), int(M_max), ctypes.byref(M), w.ctypes.data_as(dp),
+                               s.ctypes.data_as(dp), ctypes.byref(err)), "q2d_soe_fit_eps")
+    m = M.value
+    return w[0:2 * m:2] + 1j * w[1:2 * m:2], s[0:2 * m:2] + 1j * s[1:2 * m:2], m, err.value
+
+
 def _interleave(z):
     z = np.asarray(z, dtype=np.complex128)
     out = np.empty(2 * len(z))
@@ -150,7 +175,7 @@ class Plan:
     """A solver for one box, Ewald parameter and SOE table (q2d_plan_create)."""
 
     def __init__(self, box, alpha, w, s, *, rc=0.0, kc=0.0, precision="fp64", n_max,
-                 p_max=0, thin=1, validate=False, stream=None):
+                 p_max=0, thin=1, validate=False, sampler="metropolis", stream=None):
         import torch
         self._torch = torch
         lib = load_library()
@@ -161,7 +186,7 @@ class Plan:
         w = _interleave(w)
         s = _interleave(s)
         opts = _Opts(FP32 if precision == "fp32" else FP64, int(thin), int(n_max), int(p_max),
-                     1 if validate else 0)
+                     1 if validate else 0, SAMPLERS[sampler])
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
@@ -202,7 +227,8 @@ class Plan:
         if not (pos.is_cuda and q.is_cuda):
             raise ValueError("pos and q must be device tensors")
         if pos.dtype != self.dtype or q.dtype != self.dtype:
-            raise ValueError("dtype must be %s for this plan" % self.dtype)
+            raise Q2DError(Q2D_EDTYPE, "dtype %s/%s for a %s plan" % (pos.dtype, q.dtype,
+                                                                       self.dtype))
         pos = pos.contiguous()
         q = q.contiguous()
         if pos.dim() != 2 or pos.shape[1] != 3 or q.shape != (pos.shape[0],):
@@ -289,6 +315,46 @@ class Plan:
                "q2d_short_range")
         return phi, F, E
 
+    def slab(self, pos, q, sig0_bot=0.0, sig0_top=0.0, modes=None, sig_bot=None, sig_top=None):
+        """Particle-slab term of charged walls (q2d_slab): (phi, F, E) device tensors.
+        sig0_*: charge per cell of each wall (sigma A for a uniform wall);
+        modes ((n, 2) int32), sig_bot, sig_top ((n,) complex128): device tensors
+        of the walls' Fourier coefficients over one cell, or None."""
+        self._sync_stream()
+        pos, q, n, phi, F, E = self._prep(pos, q)
+        t = self._torch
+        nm, mp, bp, tp = 0, None, None, None
+        if modes is not None:
+            modes = modes.to(t.int32).contiguous()
+            sb = t.view_as_real(sig_bot.to(t.complex128).contiguous()).contiguous()
+            st = t.view_as_real(sig_top.to(t.complex128).contiguous()).contiguous()
+            if modes.dim() != 2 or modes.shape[1] != 2 or sb.shape != (modes.shape[0], 2) or \
+                    st.shape != (modes.shape[0], 2):
+                raise ValueError("modes (n, 2), sig_bot and sig_top (n,) complex")
+            nm, mp, bp, tp = modes.shape[0], modes.data_ptr(), sb.data_ptr(), st.data_ptr()
+            self._keep = (modes, sb, st)
+        _check(self._lib.q2d_slab(self._h, pos.data_ptr(), q.data_ptr(), n, nm, mp, bp, tp,
+                                  float(sig0_bot), float(sig0_top), phi.data_ptr(),
+                                  F.data_ptr(), E.data_ptr()), "q2d_slab")
+        return phi, F, E
+
+    def langevin_step(self, pos, mom, forces, dt, gamma, kT, seed, step, stage, mass=None):
+        """One BAOAB stage (q2d_langevin_step) in place on pos (stage 0) and mom.
+        forces: up to three (N, 3) device tensors summed."""
+        self._sync_stream()
+        for tt in [pos, mom] + list(forces) + ([mass] if mass is not None else []):
+            if tt.dtype != self.dtype:
+                raise Q2DError(Q2D_EDTYPE, "langevin_step")
+            if not tt.is_contiguous():
+                raise ValueError("tensors must be contiguous")
+        fs = [f.data_ptr() for f in forces] + [None] * (3 - len(forces))
+        _check(self._lib.q2d_langevin_step(self._h, pos.data_ptr(), mom.data_ptr(),
+                                           mass.data_ptr() if mass is not None else None,
+                                           mom.shape[0], fs[0], fs[1], fs[2], float(dt),
+                                           float(gamma), float(kT), ctypes.c_uint64(seed),
+                                           ctypes.c_uint64(step), int(stage)),
+               "q2d_langevin_step")
+
     def check(self):
         """Wait for the stream; return the device-side data status code (0 = ok)."""
         return int(self._lib.q2d_plan_check(self._h))
@@ -342,7 +408,7 @@ class Batch:
         w = _interleave(w)
         s = _interleave(s)
         opts = _Opts(FP32 if precision == "fp32" else FP64, int(thin), max(self.N, 1),
-                     int(p_max), 1 if validate else 0)
+                     int(p_max), 1 if validate else 0, 0)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
@@ -377,8 +443,11 @@ class Batch:
 
     def _io(self, pos, q):
         t = self._torch
-        if not (pos.is_cuda and q.is_cuda) or pos.dtype != self.dtype or q.dtype != self.dtype:
-            raise ValueError("pos, q must be device tensors of the batch's dtype")
+        if not (pos.is_cuda and q.is_cuda):
+            raise ValueError("pos, q must be device tensors")
+        if pos.dtype != self.dtype or q.dtype != self.dtype:
+            raise Q2DError(Q2D_EDTYPE, "dtype %s/%s for a %s batch" % (pos.dtype, q.dtype,
+                                                                        self.dtype))
         pos = pos.contiguous()
         q = q.contiguous()
         if pos.shape != (self.N, 3) or q.shape != (self.N,):

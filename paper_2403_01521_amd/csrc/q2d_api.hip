@@ -26,6 +26,12 @@ q2d_status ensure(Plan *p, Buf &b, size_t bytes) {
     if (b.p) {
         if (hipStreamSynchronize(p->stream) != hipSuccess) return Q2D_EDEVICE;
         if (p->side && hipStreamSynchronize(p->side) != hipSuccess) return Q2D_EDEVICE;
+        // a captured step holds the old address: drop the graph (replay then
+        // returns Q2D_EUNSUPPORTED until the next capture)
+        if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->graph_exec = nullptr;
+        p->graph = nullptr;
         (void)hipFree(b.p);
         b.p = nullptr;
         b.bytes = 0;
@@ -288,6 +294,8 @@ q2d_status plan_init(Plan *p, double Lx, double Ly, double Lz, double alpha, dou
     if (opts->n_max <= 0 || opts->n_max > ((int64_t)1 << 31) - 1 || opts->p_max < 0 ||
         opts->thin < 0)
         return Q2D_EINVAL;
+    if (opts->sampler != Q2D_SAMPLER_METROPOLIS && opts->sampler != Q2D_SAMPLER_IID)
+        return Q2D_EINVAL;
     if (r_c > 0 && r_c > 0.5 * std::min(Lx, Ly)) return Q2D_EINVAL;
     // SOE table: conjugate-closed, Re s > 0, no real node
     std::vector<cd> wc(M), sc(M);
@@ -385,6 +393,14 @@ q2d_status plan_init(Plan *p, double Lx, double Ly, double Lz, double alpha, dou
     const double A = Lx * Ly;
     q2d_status st = ensure(p, p->status, 64);
     if (st != Q2D_OK) return st;
+    if (opts->sampler == Q2D_SAMPLER_IID && opts->p_max > 0) {
+        std::vector<double> tab;
+        iid_tables(alpha, Lx, Ly, tab, &p->iid_mxm, &p->iid_mym);
+        if ((st = ensure(p, p->iid_tab, tab.size() * sizeof(double))) != Q2D_OK) return st;
+        if (hipMemcpy(p->iid_tab.p, tab.data(), tab.size() * sizeof(double),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return Q2D_EDEVICE;
+    }
     k_zero_status<<<1, 1, 0, p->stream>>>((int *)p->status.p, (double *)((char *)p->status.p + 16));
 
     // exact-k half-lattice mode table
@@ -460,11 +476,12 @@ void plan_release(Plan *p) {
         p->pend_ev[w].clear();
     }
     Buf *bufs[] = {&p->exact_modes, &p->exact_coef, &p->rb_modes, &p->rb_coef, &p->rb_work,
+                   &p->iid_tab,
                    &p->user_modes, &p->user_w, &p->user_coef, &p->s_g, &p->fq,
                    &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
                    &p->s_uy, &p->s_z, &p->s_q, &p->spans, &p->agg, &p->carry_tmp, &p->outk, &p->spans0,
                    &p->agg0, &p->carry_tmp0, &p->phi0, &p->fz0, &p->epart, &p->inv, &p->status,
-                   &p->cell_start, &p->cell_count, &p->cell_idx, &p->cell_tmp, &p->rep_box,
+                   &p->cell_start, &p->row_tiles, &p->cell_rec, &p->tile_e, &p->rep_box,
                    &p->rep_H, &p->rep_diag, &p->rep_tpa, &p->rep_of, &p->rep_off, &p->rep_poff,
                    &p->seg_rep, &p->pperm, &p->epart_rep, &p->step_ctr, &p->recs};
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -496,6 +513,7 @@ const char *q2d_status_string(q2d_status st) {
         case Q2D_EDEVICE: return "HIP runtime error";
         case Q2D_ESAMPLER: return "mode sampler found no non-zero proposal";
         case Q2D_EUNSUPPORTED: return "plan was created without support for this call";
+        case Q2D_EDTYPE: return "element type differs from the plan's precision";
     }
     return "unknown status";
 }
@@ -521,6 +539,20 @@ q2d_status q2d_soe_fit(int32_t M, double *w, double *s, double *sup_error) {
     }
     if (sup_error) *sup_error = sup_err(best, 40000);
     return Q2D_OK;
+}
+
+q2d_status q2d_soe_fit_eps(double eps, int32_t M_max, int32_t *M, double *w, double *s,
+                           double *sup_error) {
+    if (!M || !w || !s || !(eps > 0) || M_max < 2 || M_max > 64) return Q2D_EINVAL;
+    double e = 0.0;
+    for (int m = 2; m <= M_max; m += 2) {
+        const q2d_status st = q2d_soe_fit(m, w, s, &e);
+        if (st != Q2D_OK) return st;
+        *M = m;
+        if (sup_error) *sup_error = e;
+        if (e <= eps) return Q2D_OK;
+    }
+    return Q2D_ECAPACITY;
 }
 
 q2d_status q2d_plan_create(double Lx, double Ly, double Lz, double alpha, double r_c, double k_c,
@@ -594,14 +626,12 @@ q2d_status q2d_long_range(q2d_plan_t p, const void *pos, const void *q, int64_t 
     return st;
 }
 
-q2d_status q2d_rbm_step(q2d_plan_t p, const void *pos, const void *q, int64_t N, int32_t P,
-                        uint64_t seed, uint64_t step, void *phi, void *F, double *E,
-                        int32_t *modes_out) {
-    q2d_status st = check_io(p, pos, q, N);
-    if (st != Q2D_OK) return st;
-    if (P < 1) return Q2D_EINVAL;
-    if (p->opts.p_max <= 0) return Q2D_EUNSUPPORTED;
-    if (P > p->opts.p_max) return Q2D_ECAPACITY;
+// The random-batch step after the argument checks (shared by q2d_rbm_step and
+// its allocation-free variant).
+static q2d_status rbm_step_body(q2d_plan_t p, const void *pos, const void *q, int64_t N,
+                                int32_t P, uint64_t seed, uint64_t step, void *phi, void *F,
+                                double *E, int32_t *modes_out) {
+    q2d_status st;
     tstart(p, 4);
     // the sampler runs on the side stream while the main stream sorts
     const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
@@ -631,6 +661,23 @@ q2d_status q2d_rbm_step(q2d_plan_t p, const void *pos, const void *q, int64_t N,
     st = epilogue(p, N, nch, p->diag_rb, true, phi, F, E);
     tstop(p, 4);
     return st;
+}
+
+static q2d_status check_rbm(q2d_plan_t p, const void *pos, const void *q, int64_t N, int32_t P) {
+    q2d_status st = check_io(p, pos, q, N);
+    if (st != Q2D_OK) return st;
+    if (P < 1) return Q2D_EINVAL;
+    if (p->opts.p_max <= 0) return Q2D_EUNSUPPORTED;
+    if (P > p->opts.p_max) return Q2D_ECAPACITY;
+    return Q2D_OK;
+}
+
+q2d_status q2d_rbm_step(q2d_plan_t p, const void *pos, const void *q, int64_t N, int32_t P,
+                        uint64_t seed, uint64_t step, void *phi, void *F, double *E,
+                        int32_t *modes_out) {
+    const q2d_status st = check_rbm(p, pos, q, N, P);
+    if (st != Q2D_OK) return st;
+    return rbm_step_body(p, pos, q, N, P, seed, step, phi, F, E, modes_out);
 }
 
 q2d_status q2d_long_range_vjp(q2d_plan_t p, const void *pos, const void *q, const void *g,

@@ -126,6 +126,7 @@ q2d_status q2d_batch_create(int32_t R, const double *boxes, const int64_t *n, do
     *out = nullptr;
     if (R < 1 || R > 65536 || !boxes || !n || !opts) return Q2D_EINVAL;
     if (opts->p_max < 1) return Q2D_EINVAL;
+    if (opts->sampler != Q2D_SAMPLER_METROPOLIS) return Q2D_EUNSUPPORTED;
     int64_t Ntot = 0;
     for (int r = 0; r < R; ++r) {
         const double Lx = boxes[3 * r], Ly = boxes[3 * r + 1], Lz = boxes[3 * r + 2];

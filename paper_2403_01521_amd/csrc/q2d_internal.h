@@ -48,6 +48,32 @@ struct PairParams {
     int rep_of[2 * MAX_PAIRS];                          // pair index if representative, else -1
 };
 
+// Philox4x32-10 (Salmon et al., SC'11): multipliers 0xD2511F53, 0xCD9E8D57,
+// key increments 0x9E3779B9, 0xBB67AE85.
+__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// uniform in (0, 1) from 53 bits of two words
+__device__ inline double u53(uint32_t a, uint32_t b) {
+    const uint64_t v = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
+    return ((double)v + 0.5) * 0x1p-53;
+}
+
 // Number of real fields per mode in a coefficient table:
 //   0 kx, 1 ky, 2 k, 3 omega, 4 ak, 5 akd, then per pair l: al.re al.im ald.re ald.im
 inline int coef_fields(int mh) { return 6 + 4 * mh; }
@@ -89,6 +115,8 @@ struct Plan {
     Buf rb_modes;     // int32 [2][p_pad]
     Buf rb_coef;      // T [fields][p_pad]
     Buf rb_work;      // sampler work arrays
+    Buf iid_tab;      // i.i.d. sampler: cumulative tables (FP64), built at creation
+    int iid_mxm = 0, iid_mym = 0;
 
     // sorting and sorted data
     Buf keys_a, keys_b, vals_a, vals_b, hist;
@@ -116,8 +144,9 @@ struct Plan {
     bool inv_ready = false;    // inv already enqueued for the current call (side stream)
     Buf status;                // int32 device status word
 
-    // short range
-    Buf cell_start, cell_count, cell_idx, cell_tmp;
+    // short range: cell starts, per-row tile offsets, cell-sorted records,
+    // per-tile energy partials
+    Buf cell_start, row_tiles, cell_rec, tile_e;
 
     // replica batch (R > 0): R independent systems of fixed sizes in one plan.
     // Inputs are concatenated by replica; after the sort each replica occupies
@@ -183,6 +212,11 @@ void tstop(Plan *p, int which);
 // ----------------------------------------------------------------------------
 // validation + key staging + stable radix sort by z + gather of sorted SoA
 q2d_status sort_and_stage(Plan *p, const void *pos, const void *q, int64_t N);
+// stable LSD radix sort (8-bit digits, `passes` of them) of N uint32 keys in
+// p->keys_a with values in p->vals_a (keys_b, vals_b, hist: scratch); returns
+// where the sorted keys and values ended up
+q2d_status radix_sort_u32(Plan *p, int64_t N, int passes, uint32_t **keys_out,
+                          int32_t **vals_out);
 // replica batches: sort by (replica, z) into the padded segment layout
 q2d_status sort_and_stage_batch(Plan *p, const void *pos, const void *q);
 
@@ -190,6 +224,8 @@ q2d_status sort_and_stage_batch(Plan *p, const void *pos, const void *q);
 q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_pad,
                             const double *weights_dev, double weight_const, void *coef);
 
+// cumulative tables of the i.i.d. mode sampler (host)
+void iid_tables(double alpha, double Lx, double Ly, std::vector<double> &tab, int *mxm, int *mym);
 // random-batch sampler: writes p->rb_modes and p->rb_coef for P modes
 q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step);
 // replica batches: P modes per replica ([r][2][p_pad], [r][fields][p_pad]);

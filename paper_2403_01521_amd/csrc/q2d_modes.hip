@@ -17,6 +17,8 @@
 // random numbers from Philox4x32-10.  Proposals are independent of the chain
 // state, so they are drawn in parallel and only the accept/reject walk runs
 // sequentially.
+#include <cmath>
+
 #include "q2d_internal.h"
 
 namespace q2d {
@@ -82,32 +84,6 @@ __global__ __launch_bounds__(256) void k_mode_coefs(const int32_t *__restrict__ 
     coef[3 * n_pad + m] = (T)om;
     coef[4 * n_pad + m] = (T)ak;
     coef[5 * n_pad + m] = (T)(-k * ak);
-}
-
-// Philox4x32-10 (Salmon et al., SC'11): multipliers 0xD2511F53, 0xCD9E8D57,
-// key increments 0x9E3779B9, 0xBB67AE85.
-__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-// uniform in (0, 1) from 53 bits of two words
-__device__ inline double u53(uint32_t a, uint32_t b) {
-    const uint64_t v = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
-    return ((double)v + 0.5) * 0x1p-53;
 }
 
 // proposal probability of one axis (App. G), as differences of erfc in the tails
@@ -253,7 +229,75 @@ __global__ __launch_bounds__(1024) void k_sample(int P, int D, uint64_t seed, ui
     }
 }
 
+// Exact i.i.d. draws from h(k) over k != 0 (the alternative to the chain of
+// App. G).  h factorises into g_x(m_x) g_y(m_y) with g(m) = e^{-(pi m/(alpha L))^2};
+// draw i inverts two cumulative tables with the two 53-bit uniforms of one
+// Philox block (counter (i, step, stream 2)): m_x from its marginal given
+// m != (0, 0) (weights g_x(m) (Z_y - [m = 0])), then m_y from g_y, or from g_y
+// without m_y = 0 when m_x = 0.  tab = [cdf_x (2 mxm + 1)][cdf_y (2 mym + 1)]
+// [cdf_y without 0 (2 mym + 1)].
+__device__ inline int first_at_least(const double *c, int n, double u) {
+    int lo = 0, hi = n - 1;  // c[n - 1] = 1 > u
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (c[mid] >= u)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_sample_iid(int P, uint64_t seed, uint64_t step,
+                                                    const double *__restrict__ tab, int mxm,
+                                                    int mym, int32_t *__restrict__ modes,
+                                                    int p_pad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p_pad) return;
+    if (i >= P) {
+        modes[i] = 0;
+        modes[p_pad + i] = 0;
+        return;
+    }
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)step, (uint32_t)(step >> 32), 2u};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const int nx = 2 * mxm + 1, ny = 2 * mym + 1;
+    const int mx = first_at_least(tab, nx, u53(c[0], c[1])) - mxm;
+    const double *cy = tab + nx + (mx == 0 ? ny : 0);
+    const int my = first_at_least(cy, ny, u53(c[2], c[3])) - mym;
+    modes[i] = mx;
+    modes[p_pad + i] = my;
+}
+
 }  // namespace
+
+// Cumulative tables of the i.i.d. sampler (host, FP64), in the layout
+// k_sample_iid reads; axis ranges |m| <= mxm, mym cover g(m) >= 1e-18.
+void iid_tables(double alpha, double Lx, double Ly, std::vector<double> &tab, int *mxm, int *mym) {
+    const double PI = 3.14159265358979323846;
+    const double kmax = 2.0 * alpha * std::sqrt(std::log(1e18));
+    *mxm = (int)std::ceil(kmax * Lx / (2 * PI));
+    *mym = (int)std::ceil(kmax * Ly / (2 * PI));
+    auto g = [&](int m, double L) {
+        const double t = PI * m / (alpha * L);
+        return std::exp(-t * t);
+    };
+    double zy = 0.0;
+    for (int m = -*mym; m <= *mym; ++m) zy += g(m, Ly);
+    auto cumulate = [&](int mm, auto wfun) {
+        const size_t b = tab.size();
+        double run = 0.0;
+        for (int m = -mm; m <= mm; ++m) {
+            run += wfun(m);
+            tab.push_back(run);
+        }
+        for (size_t j = b; j < tab.size(); ++j) tab[j] /= run;
+    };
+    tab.clear();
+    cumulate(*mxm, [&](int m) { return g(m, Lx) * (m == 0 ? zy - 1.0 : zy); });
+    cumulate(*mym, [&](int m) { return g(m, Ly); });
+    cumulate(*mym, [&](int m) { return m == 0 ? 0.0 : g(m, Ly); });
+}
 
 q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_pad,
                             const double *weights_dev, double weight_const, void *coef) {
@@ -271,6 +315,21 @@ q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_
 }
 
 q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step) {
+    const double PI = 3.14159265358979323846;
+    if (p->opts.sampler == Q2D_SAMPLER_IID) {
+        const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
+        q2d_status st;
+        if ((st = ensure(p, p->rb_modes, (size_t)2 * p_pad * sizeof(int32_t))) != Q2D_OK) return st;
+        const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+        if ((st = ensure(p, p->rb_coef, (size_t)coef_fields(p->mh) * p_pad * tsz)) != Q2D_OK)
+            return st;
+        k_sample_iid<<<(p_pad + 255) / 256, 256, 0, p->stream>>>(
+            P, seed, step, (const double *)p->iid_tab.p, p->iid_mxm, p->iid_mym,
+            (int32_t *)p->rb_modes.p, p_pad);
+        if (hipGetLastError() != hipSuccess) return Q2D_EDEVICE;
+        return build_mode_coefs(p, (const int32_t *)p->rb_modes.p, P, p_pad, nullptr,
+                                PI / (p->Lx * p->Ly) * p->H / P, p->rb_coef.p);
+    }
     const int D = p->opts.thin > 0 ? p->opts.thin : 1;
     const int n = SAMPLER_RESERVE + P * D;
     const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
@@ -288,7 +347,6 @@ q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step) {
                                          (int32_t *)p->rb_modes.p, p_pad, (int *)p->status.p,
                                          nullptr, nullptr);
     if (hipGetLastError() != hipSuccess) return Q2D_EDEVICE;
-    const double PI = 3.14159265358979323846;
     return build_mode_coefs(p, (const int32_t *)p->rb_modes.p, P, p_pad, nullptr,
                             PI / (p->Lx * p->Ly) * p->H / P, p->rb_coef.p);
 }

@@ -1224,8 +1224,15 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
     const int mh = p->mh;
     const int32_t *seg_rep = p->R ? (const int32_t *)p->seg_rep.p : nullptr;
     const int64_t MB = ((int64_t)std::max(env_int("Q2D_MODE_BATCH", 1024), 1) + WAVE - 1) / WAVE * WAVE;
-    const int64_t nfull = (nmodes / WAVE) * WAVE;
-    const int rem = (int)(nmodes - nfull);
+    int64_t nfull = (nmodes / WAVE) * WAVE;
+    int rem = (int)(nmodes - nfull);
+    // a remainder of 61..63 modes rounds up to a whole group: it runs as one
+    // more F = 1 group whose last lanes read the tables' zero-weight padding
+    // (every table is padded to a multiple of 64 columns)
+    if (rem > WAVE - SUB) {
+        nfull += WAVE;
+        rem = 0;
+    }
     const int rem4 = (rem + 3) & ~3;  // band lanes, padded to a multiple of 4
     const int nbatch = nfull > 0 ? (int)((nfull + MB - 1) / MB) : 1;
     const int ngroups0 = (int)(std::min(nfull, MB) / WAVE);

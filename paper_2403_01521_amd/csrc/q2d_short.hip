@@ -1,17 +1,44 @@
-// Real-space part of the Ewald split (Sec. 2.2, eq. phi_s) with a uniform cell list:
-//   phi_s,i = sum over images m and j (j != i for m = 0), |r_ij + M| <= r_c, of q_j erfc(alpha r)/r
+// Real-space part of the Ewald split (Sec. 2.2, eq. phi_s), O(N) by a cell list:
+//   phi_s,i = sum over images m and j (j != i for m = 0), |r_ij + M| < r_c, of q_j erfc(alpha r)/r
 //   F_s,i   = q_i sum q_j [erfc(alpha r)/r^2 + (2 alpha/sqrt(pi)) e^{-alpha^2 r^2}/r] (r_ij + M)/r
-// With r_c <= min(Lx, Ly)/2 at most one image of a particle lies within r_c,
-// so the minimum-image displacement in x and y is exact.  Cells have edge
-// >= r_c; the 3 x 3 x 3 neighbourhood (periodic in x, y; not in z) is
-// visited with duplicate cells removed when a direction has fewer than 3 cells.
-// Arithmetic is FP64 whatever the plan precision; each cell's particles are
-// ordered by index so results are deterministic.
+// The real-space sum is short ranged, so only neighbours within r_c count
+// (the remark after eq. rckc: cell lists make it O(N)); with alpha chosen by
+// eq. 59 and r_c = s/alpha (eq. rckc) the work per particle is O(1).
+//
+// Layout (MI355X):
+//  * cells of edge >= r_c/2 in x, y, z, keyed (cy, cx, cz) with cz fastest, so
+//    a row of constant cy holds its columns in x order and each column its z
+//    cells; particles are sorted by cell with the library's stable radix sort
+//    and copied into one (x, y, z, q) record each, in cell order;
+//  * a wave takes a tile of <= 64 consecutive targets inside one row; the
+//    candidates of the tile are the 5 rows cy - 2 .. cy + 2, in each the
+//    columns cx_lo - 2 .. cx_hi + 2 and the z cells within 2 of the tile's,
+//    visited as contiguous index ranges with an explicit periodic image shift
+//    per range.  r_c <= min(Lx, Ly)/2 (checked at plan creation) puts at most
+//    one image of a pair within r_c, so ranges that repeat a column with
+//    another shift add nothing twice;
+//  * candidates are loaded 64 at a time, one per lane, and broadcast with
+//    readlane: every lane first builds a bit mask of the candidates within r_c
+//    of its target, then evaluates only those pairs (lanes fetch their own
+//    candidate with a lane permute), so the erfc work is not paid for the
+//    ~60% of candidates outside the sphere;
+//  * FP32 plans: erfc(x) = erfcx(x) e^{-x^2}, with erfcx as a Chebyshev series
+//    in u = 1/(1 + x/2) on [0, alpha r_c] fitted in FP64 at each call from the
+//    definition (relative error below 1e-9 for alpha r_c <= 8) and e^{-x^2}
+//    shared with the force term; FP64 plans call the library erfc.  Each
+//    chunk's pair terms are summed in the plan's precision and added to FP64
+//    accumulators; every target sums its pairs in a fixed order, the energy in
+//    a fixed reduction order (deterministic).
+#include <cmath>
+
 #include "q2d_internal.h"
 
 namespace q2d {
 
 namespace {
+
+constexpr int SR_WAVES = 4;       // independent waves per work-group
+constexpr int CHEB_DEG = 12;      // degree of the erfcx series
 
 struct Grid {
     int nx, ny, nz;
@@ -19,39 +46,66 @@ struct Grid {
 };
 
 template <typename T>
-__device__ inline int cell_of(const T *pos, int64_t i, const Grid &g, double &x, double &y,
-                              double &z) {
-    x = (double)pos[3 * i];
-    y = (double)pos[3 * i + 1];
-    z = (double)pos[3 * i + 2];
-    x -= floor(x / g.Lx) * g.Lx;
-    y -= floor(y / g.Ly) * g.Ly;
-    int cx_ = min(g.nx - 1, max(0, (int)(x / g.hx)));
-    int cy_ = min(g.ny - 1, max(0, (int)(y / g.hy)));
-    int cz_ = min(g.nz - 1, max(0, (int)(z / g.hz)));
-    return (cz_ * g.ny + cy_) * g.nx + cx_;
+struct alignas(4 * sizeof(T)) Rec4 {
+    T x, y, z, q;
+};
+
+struct ShortArgs {
+    Grid g;
+    double alpha, rc;
+    double u0, uscale;             // t = (u - u0) * uscale - 1 maps [u0, 1] to [-1, 1]
+    double cheb[CHEB_DEG + 1];     // erfcx(x) ~ sum_k cheb[k] T_k(t), cheb[0] halved
+    int ntile_max;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cell_stage(const T *__restrict__ pos,
+                                                    const T *__restrict__ q, int64_t N, Grid g,
+                                                    uint32_t *__restrict__ keys,
+                                                    int32_t *__restrict__ vals,
+                                                    Rec4<T> *__restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    T x = pos[3 * i], y = pos[3 * i + 1];
+    const T z = pos[3 * i + 2];
+    x -= floor(x / (T)g.Lx) * (T)g.Lx;
+    y -= floor(y / (T)g.Ly) * (T)g.Ly;
+    const int cx = min(g.nx - 1, max(0, (int)((double)x / g.hx)));
+    const int cy = min(g.ny - 1, max(0, (int)((double)y / g.hy)));
+    const int cz = min(g.nz - 1, max(0, (int)((double)z / g.hz)));
+    keys[i] = ((uint32_t)cy * (uint32_t)g.nx + (uint32_t)cx) * (uint32_t)g.nz + (uint32_t)cz;
+    vals[i] = (int32_t)i;
+    rec[i] = Rec4<T>{x, y, z, q[i]};
 }
 
 template <typename T>
-__global__ void k_cell_count(const T *pos, int64_t N, Grid g, int32_t *__restrict__ cidx,
-                             int32_t *__restrict__ count) {
+__global__ __launch_bounds__(256) void k_cell_gather(const Rec4<T> *__restrict__ rec,
+                                                     const int32_t *__restrict__ perm, int64_t N,
+                                                     Rec4<T> *__restrict__ srec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    double x, y, z;
-    const int c = cell_of(pos, i, g, x, y, z);
-    cidx[i] = c;
-    atomicAdd(&count[c], 1);
+    if (i < N) srec[i] = rec[perm[i]];
 }
 
-// single block exclusive scan of cell counts
-__global__ __launch_bounds__(1024) void k_cell_scan(const int32_t *count, int ncell,
-                                                    int32_t *start, int32_t *fill) {
+// start[c] = first sorted index with key >= c, for c in [0, ncell]
+__global__ __launch_bounds__(256) void k_cell_bounds(const uint32_t *__restrict__ key, int64_t N,
+                                                     uint32_t ncell, int32_t *__restrict__ start) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > N) return;
+    const uint32_t lo = i == 0 ? 0u : key[i - 1] + 1u;
+    const uint32_t hi = i == N ? ncell : key[i];
+    for (uint32_t c = lo; c <= hi; ++c) start[c] = (int32_t)i;
+}
+
+// tiles of <= 64 targets per row: base[r] = tiles before row r, base[ny] = total
+__global__ __launch_bounds__(1024) void k_row_tiles(const int32_t *__restrict__ start, int ny,
+                                                    int row_cells, int32_t *__restrict__ base) {
     __shared__ int32_t part[1024];
     const int t = threadIdx.x;
-    const int per = (ncell + 1023) / 1024;
-    const int b0 = min(t * per, ncell), b1 = min(b0 + per, ncell);
+    const int per = (ny + 1023) / 1024;
+    const int b0 = min(t * per, ny), b1 = min(b0 + per, ny);
     int32_t s = 0;
-    for (int b = b0; b < b1; ++b) s += count[b];
+    for (int r = b0; r < b1; ++r)
+        s += (start[(r + 1) * row_cells] - start[r * row_cells] + WAVE - 1) / WAVE;
     part[t] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -61,112 +115,182 @@ __global__ __launch_bounds__(1024) void k_cell_scan(const int32_t *count, int nc
         __syncthreads();
     }
     int32_t run = t ? part[t - 1] : 0;
-    for (int b = b0; b < b1; ++b) {
-        start[b] = run;
-        fill[b] = 0;
-        run += count[b];
+    for (int r = b0; r < b1; ++r) {
+        base[r] = run;
+        run += (start[(r + 1) * row_cells] - start[r * row_cells] + WAVE - 1) / WAVE;
     }
-    if (t == 1023) start[ncell] = part[1023];
+    if (t == 1023) base[ny] = part[1023];
 }
 
-__global__ void k_cell_fill(const int32_t *cidx, int64_t N, const int32_t *start, int32_t *fill,
-                            int32_t *list) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int c = cidx[i];
-    const int at = atomicAdd(&fill[c], 1);
-    list[start[c] + at] = (int32_t)i;
+__device__ inline float bcast(float v, int j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ inline double bcast(double v, int j) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), j);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// order each cell's list by particle index (insertion sort; cells are small)
-__global__ void k_cell_order(const int32_t *start, int ncell, int32_t *list) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int b = start[c], e = start[c + 1];
-    for (int i = b + 1; i < e; ++i) {
-        const int32_t v = list[i];
-        int j = i - 1;
-        while (j >= b && list[j] > v) {
-            list[j + 1] = list[j];
-            --j;
-        }
-        list[j + 1] = v;
+// erfc(x) and e^{-x^2} for 0 <= x <= alpha r_c
+__device__ inline void erfc_gauss(const ShortArgs &a, float x, float &ec, float &g) {
+    g = __builtin_amdgcn_exp2f(-1.4426950408889634f * x * x);
+    const float u = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+    const float t = fmaf((float)a.uscale, u - (float)a.u0, -1.0f), t2 = 2.0f * t;
+    float b1 = 0.f, b2 = 0.f;
+#pragma unroll
+    for (int k = CHEB_DEG; k >= 1; --k) {
+        const float b0 = fmaf(t2, b1, (float)a.cheb[k] - b2);
+        b2 = b1;
+        b1 = b0;
     }
+    ec = fmaf(t, b1, (float)a.cheb[0] - b2) * g;
 }
+__device__ inline void erfc_gauss(const ShortArgs &, double x, double &ec, double &g) {
+    g = exp(-x * x);
+    ec = erfc(x);
+}
+__device__ inline float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ inline double rsq(double v) { return 1.0 / sqrt(v); }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_short(const T *__restrict__ pos, const T *__restrict__ q,
-                                               int64_t N, Grid g, double alpha, double rc,
-                                               const int32_t *__restrict__ start,
-                                               const int32_t *__restrict__ list,
-                                               T *__restrict__ phi, T *__restrict__ F,
-                                               double *__restrict__ epart) {
-    __shared__ double red[256];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double e = 0.0;
-    if (i < N) {
-        double xi, yi, zi;
-        const int ci = cell_of(pos, i, g, xi, yi, zi);
-        const int cxi = ci % g.nx, cyi = (ci / g.nx) % g.ny, czi = ci / (g.nx * g.ny);
-        const double qi = (double)q[i];
-        double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-        const double two_a_sqpi = 2.0 * alpha / sqrt(3.14159265358979323846);
-        int xs[3], ys[3];
-        int nxs = 0, nys = 0;
-        for (int d = -1; d <= 1; ++d) {
-            const int c = ((cxi + d) % g.nx + g.nx) % g.nx;
-            bool dup = false;
-            for (int k = 0; k < nxs; ++k) dup |= xs[k] == c;
-            if (!dup) xs[nxs++] = c;
+__global__ __launch_bounds__(SR_WAVES *WAVE) void k_short_tiles(
+    const ShortArgs a, const Rec4<T> *__restrict__ srec, const uint32_t *__restrict__ skey,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ start,
+    const int32_t *__restrict__ row_base, T *__restrict__ phi, T *__restrict__ F,
+    double *__restrict__ tile_e) {
+    const Grid &g = a.g;
+    const int lane = threadIdx.x % WAVE;
+    const int tile = blockIdx.x * SR_WAVES + (int)(threadIdx.x / WAVE);
+    if (tile >= a.ntile_max) return;
+    const int ntiles = row_base[g.ny];
+    if (tile >= ntiles) {
+        if (lane == 0) tile_e[tile] = 0.0;
+        return;
+    }
+    // the tile's row: last r with row_base[r] <= tile (rows may hold no tile)
+    int lo = 0, hi = g.ny - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_base[mid] <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int cy = lo;
+    const int row_cells = g.nx * g.nz;
+    const int i0 = start[cy * row_cells] + WAVE * (tile - row_base[cy]);
+    const int i1 = min(i0 + WAVE, start[(cy + 1) * row_cells]);
+    const int nt = i1 - i0;  // 1..64 targets
+    const bool valid = lane < nt;
+    const int i = valid ? i0 + lane : i0;
+    const Rec4<T> me = srec[i];
+    const uint32_t key = skey[i];
+    const int cx = (int)((key / (uint32_t)g.nz) % (uint32_t)g.nx), cz = (int)(key % (uint32_t)g.nz);
+    // columns of the tile (targets are ordered by column) and its z cells
+    const int cx_lo = __builtin_amdgcn_readlane(cx, 0);
+    const int cx_hi = __builtin_amdgcn_readlane(cx, nt - 1);
+    int zmn = cz, zmx = cz;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        zmn = min(zmn, __shfl_xor(zmn, o));
+        zmx = max(zmx, __shfl_xor(zmx, o));
+    }
+    const int z0 = max(0, zmn - 2), z1 = min(g.nz - 1, zmx + 2);
+    const bool zfull = z0 == 0 && z1 == g.nz - 1;
+    const T rc2 = (T)(a.rc * a.rc);
+    const T alpha = (T)a.alpha;
+    const T c2a = (T)(2.0 * a.alpha / 1.7724538509055160273);
+    double aphi = 0.0, afx = 0.0, afy = 0.0, afz = 0.0;
+
+    // one range of candidates [b, e) seen through the periodic shift (sx, sy)
+    auto range = [&](int b, int e, T sx, T sy) {
+        for (int c0 = b; c0 < e; c0 += WAVE) {
+            const int nc = min(WAVE, e - c0);
+            const Rec4<T> cd = srec[c0 + (lane < nc ? lane : 0)];
+            const T cxp = cd.x + sx, cyp = cd.y + sy, czp = cd.z, cq = cd.q;
+            // in-range mask of this lane's target over the nc candidates
+            uint32_t mlo = 0, mhi = 0;
+            for (int j = 0; j < nc; ++j) {
+                const T dx = me.x - bcast(cxp, j), dy = me.y - bcast(cyp, j),
+                        dz = me.z - bcast(czp, j);
+                const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                const bool in = r2 < rc2 && r2 > (T)0;
+                if (j < 32)
+                    mlo |= in ? (1u << j) : 0u;
+                else
+                    mhi |= in ? (1u << (j - 32)) : 0u;
+            }
+            if (!valid) mlo = mhi = 0;
+            // the pairs: every lane takes its next candidate each round
+            T sp = 0, sfx = 0, sfy = 0, sfz = 0;
+            while (__any(mlo | mhi)) {
+                const bool has = (mlo | mhi) != 0;
+                const int j = mlo ? __builtin_ctz(mlo) : (mhi ? 32 + __builtin_ctz(mhi) : lane);
+                if (mlo)
+                    mlo &= mlo - 1;
+                else if (mhi)
+                    mhi &= mhi - 1;
+                const T px = __shfl(cxp, j), py = __shfl(cyp, j), pz = __shfl(czp, j),
+                        pq = __shfl(cq, j);
+                const T dx = me.x - px, dy = me.y - py, dz = me.z - pz;
+                T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                r2 = has ? r2 : (T)1;
+                const T ri = rsq(r2);
+                T ec, gs;
+                erfc_gauss(a, alpha * (r2 * ri), ec, gs);
+                const T qj = has ? pq : (T)0;
+                const T er = ec * ri;
+                sp = fma(qj, er, sp);
+                const T fm = qj * fma(c2a, gs, er) * (ri * ri);
+                sfx = fma(fm, dx, sfx);
+                sfy = fma(fm, dy, sfy);
+                sfz = fma(fm, dz, sfz);
+            }
+            aphi += (double)sp;
+            afx += (double)sfx;
+            afy += (double)sfy;
+            afz += (double)sfz;
         }
-        for (int d = -1; d <= 1; ++d) {
-            const int c = ((cyi + d) % g.ny + g.ny) % g.ny;
-            bool dup = false;
-            for (int k = 0; k < nys; ++k) dup |= ys[k] == c;
-            if (!dup) ys[nys++] = c;
+    };
+
+    for (int dy = -2; dy <= 2; ++dy) {
+        const int yr = cy + dy;
+        const int cyr = ((yr % g.ny) + g.ny) % g.ny;
+        const T sy = (T)((double)((yr - cyr) / g.ny) * g.Ly);
+        const int row0 = cyr * row_cells;
+        // column runs with one shift each
+        int xa = cx_lo - 2;
+        const int xb = cx_hi + 2;
+        while (xa <= xb) {
+            const int per = xa >= 0 ? xa / g.nx : -((-xa + g.nx - 1) / g.nx);  // floor(xa / nx)
+            const int run_end = min(xb, (per + 1) * g.nx - 1);
+            const int ca = xa - per * g.nx, cb = run_end - per * g.nx;
+            const T sx = (T)((double)per * g.Lx);
+            if (zfull) {
+                range(start[row0 + ca * g.nz], start[row0 + cb * g.nz + g.nz], sx, sy);
+            } else {
+                for (int c = ca; c <= cb; ++c)
+                    range(start[row0 + c * g.nz + z0], start[row0 + c * g.nz + z1 + 1], sx, sy);
+            }
+            xa = run_end + 1;
         }
-        for (int dzc = -1; dzc <= 1; ++dzc) {
-            const int cz_ = czi + dzc;
-            if (cz_ < 0 || cz_ >= g.nz) continue;
-            for (int a = 0; a < nys; ++a)
-                for (int b = 0; b < nxs; ++b) {
-                    const int c = (cz_ * g.ny + ys[a]) * g.nx + xs[b];
-                    for (int t = start[c]; t < start[c + 1]; ++t) {
-                        const int64_t j = list[t];
-                        if (j == i) continue;
-                        double dx = xi - (double)pos[3 * j];
-                        double dy = yi - (double)pos[3 * j + 1];
-                        const double dz = zi - (double)pos[3 * j + 2];
-                        dx -= rint(dx / g.Lx) * g.Lx;
-                        dy -= rint(dy / g.Ly) * g.Ly;
-                        const double r2 = dx * dx + dy * dy + dz * dz;
-                        if (r2 > rc * rc || r2 == 0.0) continue;
-                        const double r = sqrt(r2);
-                        const double qj = (double)q[j];
-                        const double ec = erfc(alpha * r) / r;
-                        ph += qj * ec;
-                        const double fm = qi * qj * (ec / r + two_a_sqpi * exp(-alpha * alpha * r2) / r) / r;
-                        fx += fm * dx;
-                        fy += fm * dy;
-                        fz += fm * dz;
-                    }
-                }
-        }
-        if (phi) phi[i] = (T)ph;
+    }
+    if (valid) {
+        const int o = perm[i];
+        if (phi) phi[o] = (T)aphi;
         if (F) {
-            F[3 * i] = (T)fx;
-            F[3 * i + 1] = (T)fy;
-            F[3 * i + 2] = (T)fz;
+            const double qi = (double)me.q;
+            F[3 * (int64_t)o] = (T)(qi * afx);
+            F[3 * (int64_t)o + 1] = (T)(qi * afy);
+            F[3 * (int64_t)o + 2] = (T)(qi * afz);
         }
-        e = qi * ph;
     }
-    red[threadIdx.x] = e;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
+    // the tile's share of 1/2 sum q_i phi_i, reduced in a fixed order
+    double e = valid ? (double)me.q * aphi : 0.0;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) e += __shfl_xor(e, o);
+    if (lane == 0) tile_e[tile] = e;
 }
 
 __global__ __launch_bounds__(256) void k_sum_half(const double *part, int n, double *E) {
@@ -182,9 +306,27 @@ __global__ __launch_bounds__(256) void k_sum_half(const double *part, int n, dou
     if (threadIdx.x == 0) E[0] = 0.5 * red[0];
 }
 
-__global__ void k_zero_i32(int32_t *a, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0;
+// Chebyshev coefficients of erfcx(x) = e^{x^2} erfc(x) as a series in
+// t = (u - u0) * uscale - 1, u = 1/(1 + x/2), for x in [0, X] (interpolation
+// at the CHEB_DEG + 1 Chebyshev points, FP64)
+void erfcx_series(double X, ShortArgs &a) {
+    const double PI = 3.14159265358979323846;
+    const int n = CHEB_DEG + 1;
+    a.u0 = 1.0 / (1.0 + 0.5 * X);
+    a.uscale = 2.0 / (1.0 - a.u0);
+    double f[CHEB_DEG + 1];
+    for (int k = 0; k < n; ++k) {
+        const double t = std::cos(PI * (k + 0.5) / n);
+        const double u = a.u0 + (t + 1.0) / a.uscale;
+        const double x = 2.0 * (1.0 / u - 1.0);
+        f[k] = std::exp(x * x) * std::erfc(x);
+    }
+    for (int j = 0; j < n; ++j) {
+        double c = 0.0;
+        for (int k = 0; k < n; ++k) c += f[k] * std::cos(PI * j * (k + 0.5) / n);
+        a.cheb[j] = 2.0 / n * c;
+    }
+    a.cheb[0] *= 0.5;
 }
 
 template <typename T>
@@ -193,40 +335,63 @@ q2d_status short_impl(Plan *p, const T *pos, const T *q, int64_t N, T *phi, T *F
     g.Lx = p->Lx;
     g.Ly = p->Ly;
     g.Lz = p->Lz;
-    g.nx = max(1, (int)floor(p->Lx / p->rc));
-    g.ny = max(1, (int)floor(p->Ly / p->rc));
-    g.nz = max(1, (int)floor(p->Lz / p->rc));
-    // bound the grid so the cell arrays stay modest
-    while ((int64_t)g.nx * g.ny * g.nz > (int64_t)1 << 22) {
-        g.nx = max(1, g.nx / 2);
-        g.ny = max(1, g.ny / 2);
-        g.nz = max(1, g.nz / 2);
+    // cell edges >= r_c / 2 (a +-2 cell stencil covers r_c); coarser cells
+    // when the grid would have far more cells than particles
+    g.nx = std::max(1, (int)std::floor(2.0 * p->Lx / p->rc));
+    g.ny = std::max(1, (int)std::floor(2.0 * p->Ly / p->rc));
+    g.nz = std::max(1, (int)std::floor(2.0 * p->Lz / p->rc));
+    const int64_t cap = std::max<int64_t>(4 * N, 4096);
+    while ((int64_t)g.nx * g.ny * g.nz > cap) {
+        if (g.nx >= g.ny && g.nx >= g.nz)
+            g.nx = std::max(1, g.nx / 2);
+        else if (g.ny >= g.nz)
+            g.ny = std::max(1, g.ny / 2);
+        else
+            g.nz = std::max(1, g.nz / 2);
     }
     g.hx = p->Lx / g.nx;
     g.hy = p->Ly / g.ny;
     g.hz = p->Lz / g.nz;
-    const int ncell = g.nx * g.ny * g.nz;
+    const uint32_t ncell = (uint32_t)g.nx * g.ny * g.nz;
+    int bits = 1;
+    while (bits < 32 && ((uint64_t)1 << bits) < ncell) ++bits;
+    const int passes = (bits + 7) / 8;
+    const int ntile_max = (int)((N + WAVE - 1) / WAVE) + g.ny;
     q2d_status st;
-    if ((st = ensure(p, p->cell_count, (size_t)ncell * sizeof(int32_t))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->cell_start, (size_t)(2 * ncell + 1) * sizeof(int32_t))) != Q2D_OK)
+    if ((st = ensure(p, p->keys_a, N * sizeof(uint32_t))) != Q2D_OK ||
+        (st = ensure(p, p->keys_b, N * sizeof(uint32_t))) != Q2D_OK ||
+        (st = ensure(p, p->vals_a, N * sizeof(int32_t))) != Q2D_OK ||
+        (st = ensure(p, p->vals_b, N * sizeof(int32_t))) != Q2D_OK ||
+        (st = ensure(p, p->recs, N * sizeof(Rec4<T>))) != Q2D_OK ||
+        (st = ensure(p, p->cell_rec, N * sizeof(Rec4<T>))) != Q2D_OK ||
+        (st = ensure(p, p->cell_start, ((size_t)ncell + 1) * sizeof(int32_t))) != Q2D_OK ||
+        (st = ensure(p, p->row_tiles, ((size_t)g.ny + 1) * sizeof(int32_t))) != Q2D_OK ||
+        (st = ensure(p, p->tile_e, (size_t)ntile_max * sizeof(double))) != Q2D_OK)
         return st;
-    if ((st = ensure(p, p->cell_idx, (size_t)N * sizeof(int32_t))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->cell_tmp, (size_t)N * sizeof(int32_t))) != Q2D_OK) return st;
+    // the long-range sort shares these buffers: its order is no longer current
+    p->inv_ready = false;
     const int nb = (int)((N + 255) / 256);
-    if ((st = ensure(p, p->epart, (size_t)nb * sizeof(double))) != Q2D_OK) return st;
-    int32_t *count = (int32_t *)p->cell_count.p;
+    k_cell_stage<T><<<nb, 256, 0, p->stream>>>(pos, q, N, g, (uint32_t *)p->keys_a.p,
+                                               (int32_t *)p->vals_a.p, (Rec4<T> *)p->recs.p);
+    uint32_t *skey = nullptr;
+    int32_t *perm = nullptr;
+    if ((st = radix_sort_u32(p, N, passes, &skey, &perm)) != Q2D_OK) return st;
+    k_cell_gather<T><<<nb, 256, 0, p->stream>>>((const Rec4<T> *)p->recs.p, perm, N,
+                                                (Rec4<T> *)p->cell_rec.p);
     int32_t *start = (int32_t *)p->cell_start.p;
-    int32_t *fill = start + ncell + 1;
-    k_zero_i32<<<(ncell + 255) / 256, 256, 0, p->stream>>>(count, ncell);
-    k_cell_count<T><<<nb, 256, 0, p->stream>>>(pos, N, g, (int32_t *)p->cell_idx.p, count);
-    k_cell_scan<<<1, 1024, 0, p->stream>>>(count, ncell, start, fill);
-    k_cell_fill<<<nb, 256, 0, p->stream>>>((const int32_t *)p->cell_idx.p, N, start, fill,
-                                           (int32_t *)p->cell_tmp.p);
-    k_cell_order<<<(ncell + 255) / 256, 256, 0, p->stream>>>(start, ncell, (int32_t *)p->cell_tmp.p);
-    k_short<T><<<nb, 256, 0, p->stream>>>(pos, q, N, g, p->alpha, p->rc, start,
-                                          (const int32_t *)p->cell_tmp.p, phi, F,
-                                          (double *)p->epart.p);
-    if (E) k_sum_half<<<1, 256, 0, p->stream>>>((const double *)p->epart.p, nb, E);
+    k_cell_bounds<<<(int)((N + 1 + 255) / 256), 256, 0, p->stream>>>(skey, N, ncell, start);
+    k_row_tiles<<<1, 1024, 0, p->stream>>>(start, g.ny, g.nx * g.nz, (int32_t *)p->row_tiles.p);
+    ShortArgs a{};
+    a.g = g;
+    a.alpha = p->alpha;
+    a.rc = p->rc;
+    a.ntile_max = ntile_max;
+    erfcx_series(p->alpha * p->rc, a);
+    const int nblk = (ntile_max + SR_WAVES - 1) / SR_WAVES;
+    k_short_tiles<T><<<nblk, SR_WAVES * WAVE, 0, p->stream>>>(
+        a, (const Rec4<T> *)p->cell_rec.p, skey, perm, start, (const int32_t *)p->row_tiles.p, phi,
+        F, (double *)p->tile_e.p);
+    if (E) k_sum_half<<<1, 256, 0, p->stream>>>((const double *)p->tile_e.p, ntile_max, E);
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 

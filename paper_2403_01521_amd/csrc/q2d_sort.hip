@@ -500,6 +500,28 @@ q2d_status gather_sources(Plan *p, const void *g, int64_t N) {
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
+q2d_status radix_sort_u32(Plan *p, int64_t N, int passes, uint32_t **keys_out,
+                          int32_t **vals_out) {
+    const int ntiles = (int)((N + SORT_TILE - 1) / SORT_TILE);
+    q2d_status st = ensure(p, p->hist, ((size_t)256 * ntiles + 256) * sizeof(uint32_t));
+    if (st != Q2D_OK) return st;
+    uint32_t *hist = (uint32_t *)p->hist.p;
+    uint32_t *tot = hist + (size_t)256 * ntiles;
+    uint32_t *kin = (uint32_t *)p->keys_a.p, *kout = (uint32_t *)p->keys_b.p;
+    int32_t *vin = (int32_t *)p->vals_a.p, *vout = (int32_t *)p->vals_b.p;
+    for (int pass = 0; pass < passes && N > 0; ++pass) {
+        k_hist<uint32_t><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, N, 8 * pass, hist, ntiles);
+        k_scan_digit<<<256, 256, 0, p->stream>>>(hist, ntiles, tot);
+        k_scatter<uint32_t><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, vin, kout, vout, N,
+                                                                   8 * pass, hist, tot, ntiles);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    *keys_out = kin;
+    *vals_out = vin;
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
 q2d_status sort_and_stage(Plan *p, const void *pos, const void *q, int64_t N) {
     p->inv_ready = false;  // a new order: any earlier inverse permutation is stale
     tstart(p, 2);

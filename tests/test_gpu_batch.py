@@ -17,6 +17,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+from _parity import assert_close  # noqa: E402
+
 torch = pytest.importorskip("torch")
 
 import paper_2403_01521_amd as q2d  # noqa: E402
@@ -87,8 +89,8 @@ def test_batch_matches_single_plans(soe_tables, prec, tol):
         if counts[r] == 0:
             assert E[r] == 0.0
             continue
-        assert rel(phi[sl], ph1) < tol, (r, rel(phi[sl], ph1))
-        assert rel(F[sl], F1) < tol, (r, rel(F[sl], F1))
+        assert_close(phi[sl], ph1, tol, r)
+        assert_close(F[sl], F1, tol, r)
         assert abs(E[r] - E1) <= tol * abs(E1), (r, E[r], E1)
     b.close()
 
@@ -110,8 +112,8 @@ def test_batch_replica_vs_oracle(soe_tables):
     ref = o3.long_range(pos[sl], q[sl], box, ALPHA, w, s, modes[r],
                         soewald2d.rb_weights(P, H, box[0], box[1]), include_self_pair=False,
                         diag=D, nthreads=8)
-    assert rel(phi[sl], ref["phi"]) < 1e-10
-    assert rel(F[sl], ref["F"]) < 1e-10
+    assert_close(phi[sl], ref["phi"], 1e-10)
+    assert_close(F[sl], ref["F"], 1e-10)
     assert abs(E[r] - ref["U"]) < 1e-10 * abs(ref["U"])
     b.close()
 
@@ -126,7 +128,8 @@ def test_batch_segment_length_invariance(soe_tables):
         assert b.info()["segment"] == S
         out = run_batch(b, pos, q, torch.float64, 3, 1)
         assert np.array_equal(out[3], ref[3])
-        assert rel(out[0], ref[0]) < 1e-12 and rel(out[1], ref[1]) < 1e-12
+        assert_close(out[0], ref[0], 1e-12)
+        assert_close(out[1], ref[1], 1e-12)
         assert np.allclose(out[2], ref[2], rtol=1e-12, atol=0)
     b.close()
 
@@ -165,7 +168,7 @@ def test_batch_tune(soe_tables):
     assert S in (64, 128, 256, 512) and b.info()["segment"] == S
     out = run_batch(b, pos, q, torch.float32, 1, 1)
     assert np.array_equal(out[3], ref[3])
-    assert rel(out[1], ref[1]) < 1e-5
+    assert_close(out[1], ref[1], 1e-5)
     b.close()
 
 
@@ -185,5 +188,6 @@ def test_batch_config5_fullsize(soe_tables):
         assert np.array_equal(modes[r], m1)
         print("config5 replica %d (N=%d): F %.2e phi %.2e" % (r, counts[r], rel(F[sl], F1),
                                                              rel(phi[sl], ph1)))
-        assert rel(F[sl], F1) < 1e-5 and rel(phi[sl], ph1) < 1e-5
+        assert_close(F[sl], F1, 1e-5)
+        assert_close(phi[sl], ph1, 1e-5)
     b.close()

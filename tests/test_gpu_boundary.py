@@ -1,0 +1,243 @@
+"""The rest of the boundary against the oracle: the real-space entry point,
+configuration 1 as the full long + short Ewald2D sum, the device-side data
+checks, the i.i.d. mode sampler, the element-type status, remainders of
+61-63 modes past a multiple of 64, and FP32 ragged sizes.
+
+Bars as elsewhere: FP64 within 1e-10 of the FP64 oracle, FP32 within the
+stated tolerance, per particle as well as in norm (tests/_parity.py).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from _parity import assert_close, assert_energy, rel  # noqa: E402
+
+torch = pytest.importorskip("torch")
+
+import paper_2403_01521_amd as q2d  # noqa: E402
+import workloads as wl  # noqa: E402
+from oracle import ewald2d, lattice, rbsampler, soewald2d  # noqa: E402
+from oracle import recursion as o3  # noqa: E402
+
+
+def dev(a, dt):
+    return torch.tensor(np.asarray(a), dtype=dt, device="cuda")
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def short(box, alpha, rc, w, s, pos, q, prec):
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    plan = q2d.Plan(box, alpha, w, s, rc=rc, precision=prec, n_max=max(1, len(q)))
+    phi, F, E = plan.short_range(dev(pos, dt), dev(q, dt))
+    torch.cuda.synchronize()
+    out = host(phi), host(F), float(E.cpu()[0])
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_short_range_config1(soe_tables, prec, tol):
+    """q2d_short_range against the oracle's erfc real-space sum (Sec. 2.2,
+    eq. phi_s) at configuration 1 (r_c = 10 = L/2: images matter)."""
+    c = wl.make_config(1, dtype=np.float32 if prec == "fp32" else np.float64)
+    w, s = soe_tables[16]
+    phi, F, E = short(c["box"], c["alpha"], c["rc"], w, s, c["pos"], c["q"], prec)
+    rphi, rF = ewald2d.real_space(c["pos"], c["q"], c["box"], c["alpha"], c["rc"])
+    rE = 0.5 * float(np.asarray(c["q"], np.float64) @ rphi)
+    print("short config1", prec, assert_close(phi, rphi, tol), assert_close(F, rF, tol))
+    assert abs(E - rE) < tol * abs(rE)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_short_range_many_cells(soe_tables, prec, tol):
+    """A 10^4-particle box with many cells per axis (and three along z),
+    checked on 300 sampled particles against the oracle."""
+    box = (60.0, 45.0, 9.0)
+    pos, q = wl.random_system(10000, box, seed=404, dtype=np.float32 if prec == "fp32"
+                              else np.float64)
+    w, s = soe_tables[8]
+    alpha, rc = 0.9, 3.0
+    phi, F, E = short(box, alpha, rc, w, s, pos, q, prec)
+    tg = np.random.default_rng(1).choice(len(q), 300, replace=False)
+    rphi, rF = ewald2d.real_space(pos, q, box, alpha, rc, targets=tg)
+    print("short 1e4", prec, assert_close(phi[tg], rphi, tol), assert_close(F[tg], rF, tol))
+    # zero net force (pair forces cancel) over the whole box
+    assert np.abs(F.sum(0)).max() < 50 * tol * np.sqrt((F * F).sum())
+
+
+def test_config1_long_plus_short(soe_tables):
+    """Configuration 1's outputs (total energy, per-particle potential and
+    forces) as long + short range on the GPU, FP64: against the SOE oracle
+    (direct SOE pair sums + the erfc real-space sum) within 1e-10, and against
+    the exact Ewald2D sum (erfc real space, xi^+- Fourier modes, k = 0 and self
+    terms) within the SOE error of M = 16."""
+    c = wl.make_config(1)
+    w, s = soe_tables[16]
+    plan = q2d.Plan(c["box"], c["alpha"], w, s, rc=c["rc"], kc=c["kc"], precision="fp64",
+                    n_max=len(c["q"]))
+    pos, q = dev(c["pos"], torch.float64), dev(c["q"], torch.float64)
+    pl, Fl, El = plan.long_range(pos, q)
+    ps, Fs, Es = plan.short_range(pos, q)
+    torch.cuda.synchronize()
+    phi = host(pl) + host(ps)
+    F = host(Fl) + host(Fs)
+    E = float(El.cpu()[0]) + float(Es.cpu()[0])
+    plan.close()
+    soe = soewald2d.exact_k(c["pos"], c["q"], c["box"], c["alpha"], c["kc"], w, s)
+    sphi, sF = ewald2d.real_space(c["pos"], c["q"], c["box"], c["alpha"], c["rc"])
+    ref_phi, ref_F = soe["phi"] + sphi, soe["F"] + sF
+    ref_U = soe["U"] + 0.5 * float(c["q"] @ sphi)
+    assert_close(phi, ref_phi, 1e-10, "phi vs SOE oracle")
+    assert_close(F, ref_F, 1e-10, "F vs SOE oracle")
+    assert abs(E - ref_U) < 1e-10 * abs(ref_U)
+    ex = ewald2d.ewald2d(c["pos"], c["q"], c["box"], c["alpha"], c["rc"], c["kc"])
+    e = (rel(phi, ex["phi"]), rel(F, ex["F"]), abs(E - ex["U"]) / abs(ex["U"]))
+    print("config1 long+short vs exact Ewald2D: phi %.2e F %.2e U %.2e" % e)
+    assert_close(phi, ex["phi"], 1e-7, "phi vs exact")
+    assert_close(F, ex["F"], 1e-7, "F vs exact")
+    assert e[2] < 1e-7
+
+
+@pytest.mark.parametrize("case", ["ok", "nonneutral", "z_below", "z_above", "nan"])
+def test_device_data_checks(soe_tables, case):
+    """validate: the device reports non-neutral charges (Thm 2.1) and particles
+    outside [0, Lz] or non-finite inputs (Sec. 2.1) through q2d_plan_check,
+    for both long-range entry points; a valid system reports nothing."""
+    w, s = soe_tables[8]
+    box = (10.0, 10.0, 4.0)
+    pos, q = wl.random_system(200, box, seed=9)
+    expect = {"ok": 0, "nonneutral": q2d.Q2D_ENONNEUTRAL}.get(case, q2d.Q2D_EOUTOFBOX)
+    if case == "nonneutral":
+        q[3] += 0.5
+    elif case == "z_below":
+        pos[17, 2] = -1e-3
+    elif case == "z_above":
+        pos[17, 2] = box[2] + 1e-3
+    elif case == "nan":
+        pos[5, 0] = np.nan
+    plan = q2d.Plan(box, 0.5, w, s, kc=2.0, precision="fp64", n_max=200, p_max=8, validate=True)
+    print("validate case", case, flush=True)
+    P, Q = dev(pos, torch.float64), dev(q, torch.float64)
+    plan.long_range(P, Q)
+    assert plan.check() == expect
+    assert plan.check() == 0  # the check clears the status
+    plan.rbm_step(P, Q, 8, 1, 2)
+    assert plan.check() == expect
+    plan.close()
+
+
+def test_element_type_status(soe_tables):
+    w, s = soe_tables[8]
+    plan = q2d.Plan((10.0, 10.0, 4.0), 0.5, w, s, kc=2.0, precision="fp32", n_max=4)
+    with pytest.raises(q2d.Q2DError) as ei:
+        plan.long_range(torch.zeros((4, 3), dtype=torch.float64, device="cuda"),
+                        torch.zeros(4, dtype=torch.float64, device="cuda"))
+    assert ei.value.code == q2d.Q2D_EDTYPE
+    plan.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_iid_sampler_step(soe_tables, prec, tol):
+    """The i.i.d. sampler option: modes bit-exact with the oracle's i.i.d.
+    sampler, and the step equal to the oracle's estimator for those modes."""
+    dtn = np.float32 if prec == "fp32" else np.float64
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    c = wl.make_config(3, dtype=dtn, n_override=8000)
+    w, s = soe_tables[16]
+    box, alpha = c["box"], c["alpha"]
+    P = 100
+    plan = q2d.Plan(box, alpha, w, s, precision=prec, n_max=len(c["q"]), p_max=P, sampler="iid")
+    phi, F, E, modes = plan.rbm_step(dev(c["pos"], dt), dev(c["q"], dt), P, seed=31, step=4)
+    torch.cuda.synchronize()
+    modes = modes.cpu().numpy()
+    ref_modes = rbsampler.sample_modes_iid(31, 4, P, alpha, box[0], box[1])
+    assert np.array_equal(modes, ref_modes)
+    H = lattice.H_direct(box[0], box[1], alpha)
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    r = o3.long_range(c["pos"].astype(np.float64), c["q"].astype(np.float64), box, alpha, w, s,
+                      modes, soewald2d.rb_weights(P, H, box[0], box[1]),
+                      include_self_pair=False, diag=D, nthreads=8)
+    assert_close(host(phi), r["phi"], tol, "phi")
+    assert_close(host(F), r["F"], tol, "F")
+    assert_energy(float(E.cpu()[0]), r["U"], c["q"], r["phi"], tol)
+    # a batch plan has only the chain of App. G
+    with pytest.raises(q2d.Q2DError) as ei:
+        _batch_iid(box, alpha, w, s)
+    assert ei.value.code == q2d.Q2D_EUNSUPPORTED
+    plan.close()
+
+
+def _batch_iid(box, alpha, w, s):
+    import ctypes
+    lib = q2d.load_library()
+    wi = q2d._interleave(w)
+    si = q2d._interleave(s)
+    opts = q2d._Opts(0, 1, 10, 4, 0, 1)
+    h = ctypes.c_void_p()
+    dp = ctypes.POINTER(ctypes.c_double)
+    boxes = np.array(box, dtype=np.float64)
+    n = np.array([10], dtype=np.int64)
+    q2d._check(lib.q2d_batch_create(1, boxes.ctypes.data_as(dp),
+                                    n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), alpha,
+                                    len(wi) // 2, wi.ctypes.data_as(dp), si.ctypes.data_as(dp),
+                                    ctypes.byref(opts), None, ctypes.byref(h)), "batch iid")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("P", [61, 63, 125, 191])
+def test_mode_remainders_near_a_group(soe_tables, prec, tol, P):
+    """P with 61-63 modes past a multiple of 64: the remainder runs as a
+    padded full group; every mode must be in the result."""
+    dtn = np.float32 if prec == "fp32" else np.float64
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    c = wl.make_config(3, dtype=dtn, n_override=5000)
+    w, s = soe_tables[16]
+    box, alpha = c["box"], c["alpha"]
+    plan = q2d.Plan(box, alpha, w, s, precision=prec, n_max=len(c["q"]), p_max=P)
+    phi, F, E, modes = plan.rbm_step(dev(c["pos"], dt), dev(c["q"], dt), P, seed=3, step=P)
+    torch.cuda.synchronize()
+    modes = modes.cpu().numpy()
+    H = lattice.H_direct(box[0], box[1], alpha)
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    r = o3.long_range(c["pos"].astype(np.float64), c["q"].astype(np.float64), box, alpha, w, s,
+                      modes, soewald2d.rb_weights(P, H, box[0], box[1]),
+                      include_self_pair=False, diag=D, nthreads=8)
+    print("P=%d %s" % (P, prec), assert_close(host(F), r["F"], tol, "F"),
+          assert_close(host(phi), r["phi"], tol, "phi"),
+          assert_energy(float(E.cpu()[0]), r["U"], c["q"], r["phi"], tol))
+    plan.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 511, 513, 4097])
+def test_ragged_sizes_fp32_random_batch(soe_tables, n):
+    """FP32 random-batch steps (split-fp16 aggregate pass, FP32 sweeps) at
+    sizes around the 64-particle blocks and 512-particle segments, against
+    the FP64 oracle (O3) on the same modes."""
+    box = (12.0, 9.0, 3.0)
+    pos, q = wl.random_system(n, box, seed=700 + n, dtype=np.float32)
+    if n == 1:
+        q = np.ones(1, dtype=np.float32)  # one charge: only the j = i terms remain
+    w, s = soe_tables[16]
+    alpha, P = 0.6, 100
+    plan = q2d.Plan(box, alpha, w, s, precision="fp32", n_max=n, p_max=P)
+    phi, F, E, modes = plan.rbm_step(dev(pos, torch.float32), dev(q, torch.float32), P, seed=5,
+                                     step=n)
+    torch.cuda.synchronize()
+    modes = modes.cpu().numpy()
+    plan.close()
+    H = lattice.H_direct(box[0], box[1], alpha)
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    r = o3.long_range(pos.astype(np.float64), q.astype(np.float64), box, alpha, w, s, modes,
+                      soewald2d.rb_weights(P, H, box[0], box[1]), include_self_pair=False,
+                      diag=D, nthreads=8)
+    if n == 1:
+        assert float(F.abs().max()) == 0.0
+        assert abs(float(phi[0]) - r["phi"][0]) < 1e-6 * abs(r["phi"][0])
+        return
+    print("ragged fp32 n=%d" % n, assert_close(host(phi), r["phi"], 2e-5, "phi"),
+          assert_close(host(F), r["F"], 2e-5, "F"))
+    assert_energy(float(E.cpu()[0]), r["U"], q, r["phi"], 2e-5)

@@ -8,20 +8,27 @@ path (which does not use fp16):
 * charge scaling: q -> s q multiplies phi by s and F, E by s^2 (the method is
   linear in the sources); s = 1e6 takes |q| far past the fp16 range, s = 1e-7
   puts every source in the fp16 subnormal range without the scaling.  Both FP32
-  runs (rescaled) must match the FP64 step as closely as each other;
+  runs (rescaled) must match the FP64 oracle (O3) as closely as each other;
 * mixed magnitudes (charges 1 and 1000 in one segment) and two thin slabs with a
-  wide empty gap (long segment spans, large decay phases): FP32 against FP64 on
-  the same modes within 2e-5.
+  wide empty gap (long segment spans, large decay phases): FP32 against the
+  FP64 O(N) recursion of the oracle (O3) on the same modes within 2e-5, per
+  particle as well as in norm; for mixed magnitudes also over the unit
+  charges alone (whose sources sit near the fp16 normal range after the
+  per-segment scaling, and whose forces the +-1000 ions dominate in the norm).
 """
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
+from _parity import assert_close, rel as prel  # noqa: E402
+
 torch = pytest.importorskip("torch")
 
 import paper_2403_01521_amd as q2d  # noqa: E402
 import workloads as wl  # noqa: E402
+from oracle import lattice, soewald2d  # noqa: E402
+from oracle import recursion as o3  # noqa: E402
 
 P = 64
 
@@ -57,11 +64,16 @@ def test_charge_scaling(soe_tables, scale):
     ratio = float(np.median(qs.astype(np.float64) / q.astype(np.float64)))
     phi1, F1, E1, m1 = step(c["box"], c["alpha"], w, s, c["pos"], q, "fp32")
     phi2, F2, E2, m2 = step(c["box"], c["alpha"], w, s, c["pos"], qs, "fp32")
-    phi0, F0, E0, m0 = step(c["box"], c["alpha"], w, s, c["pos"].astype(np.float64),
-                            q.astype(np.float64), "fp64")
-    assert np.array_equal(m1, m2) and np.array_equal(m1, m0)
+    box, alpha = c["box"], c["alpha"]
+    assert np.array_equal(m1, m2)
+    H = lattice.H_direct(box[0], box[1], alpha)
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    r = o3.long_range(c["pos"].astype(np.float64), q.astype(np.float64), box, alpha, w, s, m1,
+                      soewald2d.rb_weights(P, H, box[0], box[1]), include_self_pair=False,
+                      diag=D, nthreads=8)
+    phi0, F0, E0 = r["phi"], r["F"], r["U"]
     assert np.all(np.isfinite(phi2)) and np.all(np.isfinite(F2))
-    # each FP32 run against the FP64 step on the same modes (two independent
+    # each FP32 run against the FP64 oracle on the same modes (two independent
     # FP32 roundings are not compared with each other)
     e1 = (rel(phi1, phi0), rel(F1, F0), abs(E1 - E0) / abs(E0))
     e2 = (rel(phi2 / ratio, phi0), rel(F2 / ratio**2, F0), abs(E2 / ratio**2 - E0) / abs(E0))
@@ -70,6 +82,8 @@ def test_charge_scaling(soe_tables, scale):
     for a, b in zip(e1, e2):
         assert a < 3e-5 and b < 3e-5
         assert b < 2 * a + 1e-5
+    assert_close(phi2 / ratio, phi0, 3e-5, "phi scaled")
+    assert_close(F2 / ratio**2, F0, 3e-5, "F scaled")
 
 def two_slabs(rng, n, box):
     """Half the ions in z in [0, 0.05 Lz], half in [0.95 Lz, Lz]: the middle is empty."""
@@ -100,11 +114,21 @@ def test_fp32_vs_fp64_hard_inputs(soe_tables, maker):
     pos32, q32 = pos.astype(np.float32), q.astype(np.float32)
     w, s = soe_tables[16]
     phi32, F32, E32, m32 = step(box, 0.3, w, s, pos32, q32, "fp32")
-    phi64, F64, E64, m64 = step(box, 0.3, w, s, pos32.astype(np.float64),
-                                q32.astype(np.float64), "fp64")
-    assert np.array_equal(m32, m64)
+    alpha = 0.3
+    H = lattice.H_direct(box[0], box[1], alpha)
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    r = o3.long_range(pos32.astype(np.float64), q32.astype(np.float64), box, alpha, w, s, m32,
+                      soewald2d.rb_weights(P, H, box[0], box[1]), include_self_pair=False,
+                      diag=D, nthreads=8)
+    phi64, F64, E64 = r["phi"], r["F"], r["U"]
     print("%s: phi %.2e F %.2e E %.2e" % (maker.__name__, rel(phi32, phi64), rel(F32, F64),
                                          abs(E32 - E64) / abs(E64)))
-    assert rel(phi32, phi64) < 2e-5
-    assert rel(F32, F64) < 2e-5
+    assert_close(phi32, phi64, 2e-5, "phi")
+    assert_close(F32, F64, 2e-5, "F")
     assert abs(E32 - E64) < 2e-5 * abs(E64)
+    unit = np.abs(q32) == 1.0
+    if not unit.all():
+        print("  unit charges only: phi %.2e F %.2e" % (prel(phi32[unit], phi64[unit]),
+                                                        prel(F32[unit], F64[unit])))
+        assert_close(phi32[unit], phi64[unit], 2e-5, "phi |q|=1")
+        assert_close(F32[unit], F64[unit], 2e-5, "F |q|=1")

@@ -18,6 +18,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+from _parity import assert_close  # noqa: E402
+
 torch = pytest.importorskip("torch")
 
 import paper_2403_01521_amd as q2d  # noqa: E402
@@ -71,15 +73,15 @@ def test_modes_eval_vs_pair_sums(soe_tables, prec, tol, nmodes):
                        np.zeros(0), include_self_pair=False, diag=0.0, nthreads=1)
     ref_phi, ref_F, ref_U = r["phi"] - r0["phi"], r["F"] - r0["F"], r["U"] - r0["U"]
     print("modes_eval", prec, nmodes, rel(phi, ref_phi), rel(F, ref_F))
-    assert rel(phi, ref_phi) < tol
-    assert rel(F, ref_F) < tol
+    assert_close(phi, ref_phi, tol)
+    assert_close(F, ref_F, tol)
     assert abs(E - ref_U) < tol * abs(ref_U)
     # direct pair sums (O2) on sampled targets, k = 0 and self terms off
     tg = np.random.default_rng(7).choice(len(c["q"]), 4, replace=False)
     r2 = soewald2d.long_range(c["pos"], c["q"], c["box"], c["alpha"], w, s, modes, wt, targets=tg,
                               include_self_pair=False, diag=0.0, k0=False)
-    assert rel(phi[tg], r2["phi"]) < tol
-    assert rel(F[tg], r2["F"]) < tol
+    assert_close(phi[tg], r2["phi"], tol)
+    assert_close(F[tg], r2["F"], tol)
 
 
 def test_modes_eval_edge_cases(soe_tables):
@@ -93,7 +95,8 @@ def test_modes_eval_edge_cases(soe_tables):
     wt = np.array([0.01, 5.0, 0.02])
     a = eval_modes(c, w, s, "fp64", modes, wt)
     b = eval_modes(c, w, s, "fp64", modes[[0, 2]], wt[[0, 2]])
-    assert rel(a[0], b[0]) < 1e-13 and rel(a[1], b[1]) < 1e-13
+    assert_close(a[0], b[0], 1e-13)
+    assert_close(a[1], b[1], 1e-13)
 
 
 def test_modes_eval_matches_rbm_pair_part(soe_tables):
@@ -115,8 +118,8 @@ def test_modes_eval_matches_rbm_pair_part(soe_tables):
     qq = c["q"]
     phi_pair = phi.cpu().numpy() - r0["phi"] - qq * info["diag_rb"]
     F_pair = F.cpu().numpy() - r0["F"]
-    assert rel(phi2.cpu().numpy(), phi_pair) < 1e-10
-    assert rel(F2.cpu().numpy(), F_pair) < 1e-10
+    assert_close(phi2.cpu().numpy(), phi_pair, 1e-10)
+    assert_close(F2.cpu().numpy(), F_pair, 1e-10)
     plan.close()
 
 

@@ -14,6 +14,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+from _parity import assert_close  # noqa: E402
+
 torch = pytest.importorskip("torch")
 
 import paper_2403_01521_amd as q2d  # noqa: E402
@@ -55,10 +57,11 @@ def test_split_layouts_fp64_vs_oracle(soe_tables, P, monkeypatch):
                       soewald2d.rb_weights(P, H, box[0], box[1]), include_self_pair=False,
                       diag=D, nthreads=8)
     for out in (a, b):
-        assert rel(out[0], r["phi"]) < 1e-10
-        assert rel(out[1], r["F"]) < 1e-10
+        assert_close(out[0], r["phi"], 1e-10)
+        assert_close(out[1], r["F"], 1e-10)
         assert abs(out[2] - r["U"]) < 1e-10 * abs(r["U"])
-    assert rel(a[0], b[0]) < 1e-13 and rel(a[1], b[1]) < 1e-13
+    assert_close(a[0], b[0], 1e-13)
+    assert_close(a[1], b[1], 1e-13)
 
 
 @pytest.mark.parametrize("P", [100, 37])
@@ -69,5 +72,6 @@ def test_split_layouts_fp32_agree(soe_tables, P, monkeypatch):
     b = step(c, w, s, "fp32", P, False, monkeypatch)
     assert np.array_equal(a[3], b[3])
     print("fp32 split vs joint", P, rel(a[0], b[0]), rel(a[1], b[1]))
-    assert rel(a[0], b[0]) < 2e-6 and rel(a[1], b[1]) < 2e-6
+    assert_close(a[0], b[0], 2e-6)
+    assert_close(a[1], b[1], 2e-6)
     assert abs(a[2] - b[2]) < 2e-6 * abs(b[2])

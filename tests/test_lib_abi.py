@@ -34,8 +34,9 @@ def test_library_exports_every_symbol():
 
 def test_status_strings():
     lib = q2d.load_library()
-    for code in range(9):
-        assert lib.q2d_status_string(code)
+    for code in range(10):
+        assert lib.q2d_status_string(code) != b"unknown status"
+    assert lib.q2d_status_string(10) == b"unknown status"
     assert lib.q2d_status_string(0) == b"ok"
 
 
@@ -78,3 +79,39 @@ def test_host_argument_checks():
     assert lib.q2d_plan_create(4, 4, 1, 1, 2.5, 1, 8, wi.ctypes.data_as(dp), si.ctypes.data_as(dp),
                                ctypes.byref(opts), None, ctypes.byref(h)) == 1
     assert lib.q2d_plan_destroy(None) == 1
+
+
+def test_host_soe_fit_eps():
+    """Accuracy-driven fit: the fewest even M whose sup error reaches eps
+    (Sec. 3: eps is the SOE accuracy), checked with the oracle's evaluator."""
+    x = np.linspace(0, 8, 20001)
+    for eps, M_expect in ((1e-4, None), (1e-8, None), (1e-12, None)):
+        w, s, M, err = q2d.soe_fit_eps(eps, 64)
+        assert err <= eps and M % 2 == 0 and len(w) == M
+        assert np.abs(osoe.soe_eval(w, s, x) - np.exp(-x * x)).max() <= 1.01 * eps
+        if M > 2:
+            _, _, e_less = q2d.soe_fit(M - 2)
+            assert e_less > eps
+    with pytest.raises(q2d.Q2DError) as ei:
+        q2d.soe_fit_eps(1e-30, 8)
+    assert ei.value.code == q2d.Q2D_ECAPACITY
+    lib = q2d.load_library()
+    buf = np.zeros(4)
+    M = ctypes.c_int32(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.q2d_soe_fit_eps(0.0, 2, ctypes.byref(M), buf.ctypes.data_as(dp),
+                               buf.ctypes.data_as(dp), None) == q2d.Q2D_EINVAL
+
+
+def test_host_rejects_unknown_sampler():
+    lib = q2d.load_library()
+    w, s, _ = q2d.soe_fit(8)
+    wi = np.empty(16); wi[0::2], wi[1::2] = w.real, w.imag
+    si = np.empty(16); si[0::2], si[1::2] = s.real, s.imag
+    dp = ctypes.POINTER(ctypes.c_double)
+    h = ctypes.c_void_p()
+    opts = q2d._Opts(0, 1, 100, 4, 0, 7)
+    assert lib.q2d_plan_create(10, 10, 1, 1, 0, 1, 8, wi.ctypes.data_as(dp),
+                               si.ctypes.data_as(dp), ctypes.byref(opts), None,
+                               ctypes.byref(h)) == q2d.Q2D_EINVAL
+
