@@ -125,11 +125,11 @@ def cpu_baseline(c, w, s, modes):
     o3.long_range(pos, q, box, alpha, w, s, modes[:Ps], wt[:Ps], include_self_pair=False,
                   diag=0.0, nthreads=1)
     t1 = time.perf_counter() - t0
-    nthr = os.cpu_count() or 1
+    nthr = effective_cores()
     Pa = 40
     t0 = time.perf_counter()
     o3.long_range(pos, q, box, alpha, w, s, modes[:Pa], wt[:Pa], include_self_pair=False,
-                  diag=0.0, nthreads=0)
+                  diag=0.0, nthreads=nthr)
     ta = time.perf_counter() - t0
     tg, Po = 2, 5
     t0 = time.perf_counter()
@@ -147,7 +147,10 @@ def cpu_baseline(c, w, s, modes):
                                      sample="O2 direct pair sums (numpy) for %d targets x %d "
                                             "modes (%.1f s), scaled to %d targets x %d modes"
                                             % (tg, Po, to, N, P_MODES)),
-                host_cpu=_cpu_model(), host_threads=nthr)
+                host_cpu=_cpu_model(), host_threads=nthr,
+                host_cores_note="threads = cores this process may run on: the CPU affinity "
+                                "mask, capped by the cgroup CPU quota (os.cpu_count() = %s)"
+                                % os.cpu_count())
 
 
 def replicas_report(w, s, steps):
@@ -208,6 +211,25 @@ def replicas_report(w, s, steps):
                                         "max": float(per.max())},
             "sequential_single_plans_ms": ms_seq,
             "batch_speedup_vs_sequential": ms_seq / best}
+
+
+def effective_cores():
+    """Cores this process may use: its affinity mask, capped by a cgroup v2/v1
+    CPU quota when one is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        quota, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if quota != "max":
+            n = min(n, max(1, int(int(quota) // int(period))))
+    except (OSError, ValueError):
+        try:
+            quota = int(open("/sys/fs/cgroup/cpu/cpu.cfs_quota_us").read())
+            period = int(open("/sys/fs/cgroup/cpu/cpu.cfs_period_us").read())
+            if quota > 0:
+                n = min(n, max(1, quota // period))
+        except (OSError, ValueError):
+            pass
+    return max(1, n)
 
 
 def _cpu_model():
@@ -321,7 +343,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "rbm_step N=1e6 slab 600x600x10 surface-excess, alpha=0.1, "
-                               "P=100, M=16, FP32 scans (FP64 k=0, carries, energy)",
+                               "P=100, M=16; FP32 sweeps, segment aggregates on the fp16 "
+                               "matrix cores with split (hi+lo) operands, FP64 k=0 term, "
+                               "carries and energy",
                    "N": N, "P": P_MODES, "M": M_SOE, "alpha": alpha, "box": list(box)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
