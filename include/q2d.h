@@ -147,6 +147,33 @@ q2d_status q2d_rbm_step(q2d_plan_t plan, const void *pos, const void *q, int64_t
                         int32_t *modes_out);
 
 /*
+ * q2d_rbm_step_noalloc -- q2d_rbm_step for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving or MD loops, harnesses
+ * that forbid hipMalloc.  Same arguments, checks, results and stream semantics
+ * as q2d_rbm_step (bit-identical outputs for the same inputs); the call itself
+ * allocates and frees nothing.  Its scratch (sorted copies, mode tables,
+ * aggregates and carries, per-chunk outputs, the k = 0 term, the inverse
+ * permutation) is not the plan's: it lives in one static device array of
+ * Q2D_NOALLOC_SCRATCH_BYTES per device, which every device the library runs
+ * on holds until the process ends, and whose address is looked up when the
+ * first plan is created on that device.  The need grows with N and P (M = 16,
+ * P = 100: 860 bytes per particle in FP32 up to N = 131072, fewer above as
+ * the segments lengthen, so N up to about 3.3e5 in FP32 and 1.5e5 in FP64);
+ * a call whose scratch does not fit returns Q2D_ECAPACITY before enqueuing
+ * anything.  The plan itself (created once,
+ * beforehand) keeps its own tables.  Every call on one device shares that
+ * device's array and leaves its contents behind: calls on one stream are
+ * ordered, but calls that can overlap in time on one device (two streams, or
+ * two plans on different streams) race on it and must be serialised by the
+ * caller.  Kernel timing (q2d_plan_timing_enable) records nothing for this
+ * call.
+ */
+#define Q2D_NOALLOC_SCRATCH_BYTES ((uint64_t)128 << 20)
+q2d_status q2d_rbm_step_noalloc(q2d_plan_t plan, const void *pos, const void *q, int64_t N,
+                                int32_t P, uint64_t seed, uint64_t step, void *phi, void *F,
+                                double *E, int32_t *modes_out);
+
+/*
  * Adjoint (vector-Jacobian product) of the potential of q2d_long_range /
  * q2d_rbm_step.  For weights g_i on the outputs phi_i (L = sum_i g_i phi_i):
  *   dq_j   = dL/dq_j   = sum_i g_i G(r_i, r_j) = the potential of "charges" g at r_j,

@@ -36,7 +36,8 @@ TIMER_SWEEP, TIMER_AGG, TIMER_SORT, TIMER_K0, TIMER_CALL = 0, 1, 2, 3, 4
 TIMING_ALL = 31
 
 EXPORTS = ("q2d_plan_create", "q2d_plan_destroy", "q2d_plan_set_stream", "q2d_plan_info",
-           "q2d_long_range", "q2d_rbm_step", "q2d_long_range_vjp", "q2d_rbm_step_vjp",
+           "q2d_long_range", "q2d_rbm_step", "q2d_rbm_step_noalloc", "q2d_long_range_vjp",
+           "q2d_rbm_step_vjp",
            "q2d_modes_eval", "q2d_short_range", "q2d_batch_create", "q2d_batch_destroy",
            "q2d_batch_set_stream", "q2d_batch_set_segment", "q2d_batch_info",
            "q2d_batch_rbm_step", "q2d_batch_tune", "q2d_batch_capture", "q2d_batch_replay",
@@ -89,6 +90,7 @@ def load_library(path=None):
     lib.q2d_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.q2d_long_range.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     lib.q2d_rbm_step.argtypes = [vp, vp, vp, i64, i32, u64, u64, vp, vp, vp, vp]
+    lib.q2d_rbm_step_noalloc.argtypes = [vp, vp, vp, i64, i32, u64, u64, vp, vp, vp, vp]
     lib.q2d_long_range_vjp.argtypes = [vp, vp, vp, vp, i64, vp, vp]
     lib.q2d_rbm_step_vjp.argtypes = [vp, vp, vp, vp, i64, i32, u64, u64, vp, vp]
     lib.q2d_modes_eval.argtypes = [vp, vp, vp, i64, vp, vp, i64, vp, vp, vp]
@@ -257,6 +259,39 @@ class Plan:
                                       ctypes.c_uint64(seed), ctypes.c_uint64(step),
                                       phi.data_ptr(), F.data_ptr(), E.data_ptr(),
                                       modes.data_ptr()), "q2d_rbm_step")
+        return phi, F, E, modes
+
+    def rbm_step_noalloc(self, pos, q, P, seed, step, out=None):
+        """The random-batch step through q2d_rbm_step_noalloc, whose scratch is the
+        library's static per-device array (the C call allocates no device memory).
+        out: optional preallocated (phi, F, E, modes) device tensors of the shapes
+        rbm_step returns; they are written and returned."""
+        self._sync_stream()
+        t = self._torch
+        if out is None:
+            pos, q, n, phi, F, E = self._prep(pos, q)
+            modes = t.empty((P, 2), dtype=t.int32, device=pos.device)
+        else:
+            if not (pos.is_cuda and q.is_cuda):
+                raise ValueError("pos and q must be device tensors")
+            if pos.dtype != self.dtype or q.dtype != self.dtype:
+                raise Q2DError(Q2D_EDTYPE, "dtype %s/%s for a %s plan" % (pos.dtype, q.dtype,
+                                                                           self.dtype))
+            if not (pos.is_contiguous() and q.is_contiguous()):
+                raise ValueError("pos and q must be contiguous")
+            n = pos.shape[0]
+            if pos.dim() != 2 or pos.shape[1] != 3 or q.shape != (n,):
+                raise ValueError("pos must be (N, 3) and q (N,)")
+            phi, F, E, modes = out
+            if (phi.shape != (n,) or F.shape != (n, 3) or E.numel() < 1 or
+                    modes.shape != (P, 2) or phi.dtype != self.dtype or F.dtype != self.dtype or
+                    E.dtype != t.float64 or modes.dtype != t.int32 or
+                    not all(x.is_contiguous() for x in (phi, F, E, modes))):
+                raise ValueError("out tensors do not match (N,), (N, 3), (1,) f64, (P, 2) i32")
+        _check(self._lib.q2d_rbm_step_noalloc(self._h, pos.data_ptr(), q.data_ptr(), n, int(P),
+                                              ctypes.c_uint64(seed), ctypes.c_uint64(step),
+                                              phi.data_ptr(), F.data_ptr(), E.data_ptr(),
+                                              modes.data_ptr()), "q2d_rbm_step_noalloc")
         return phi, F, E, modes
 
     def _prep_vjp(self, pos, q, g):

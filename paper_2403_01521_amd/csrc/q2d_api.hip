@@ -14,13 +14,67 @@
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 
 #include "q2d_internal.h"
 
 namespace q2d {
 
+static size_t piece(size_t bytes) { return ((bytes ? bytes : 16) + 255) & ~(size_t)255; }
+
+// an allocation-free call: lend b a piece of the arena (never allocates)
+static q2d_status arena_take(Arena &a, Buf &b, size_t bytes) {
+    int i = 0;
+    while (i < a.n && a.lent[i] != &b) ++i;
+    if (i < a.n && b.bytes >= bytes) return Q2D_OK;
+    if (i == a.n) {
+        if (a.n == Arena::CAP) return Q2D_ECAPACITY;
+        a.lent[a.n] = &b;
+        a.saved[a.n] = b;
+        ++a.n;
+    }
+    const size_t sz = piece(bytes);
+    if (a.off + sz > a.cap) return Q2D_ECAPACITY;
+    b.p = a.base + a.off;
+    b.bytes = sz;
+    a.off += sz;
+    return Q2D_OK;
+}
+
+size_t arena_need(const Reqs &q) {
+    if (q.overflow) return ~(size_t)0;
+    const Buf *seen[Reqs::CAP];
+    size_t have[Reqs::CAP];
+    int n = 0;
+    size_t total = 0;
+    for (int r = 0; r < q.n; ++r) {
+        int i = 0;
+        while (i < n && seen[i] != q.r[r].b) ++i;
+        if (i < n && have[i] >= q.r[r].bytes) continue;
+        if (i == n) seen[n++] = q.r[r].b;
+        have[i] = piece(q.r[r].bytes);
+        total += have[i];
+    }
+    return total;
+}
+
+void arena_restore(Arena &a) {
+    for (int i = a.n - 1; i >= 0; --i) *a.lent[i] = a.saved[i];
+    a.n = 0;
+}
+
+q2d_status ensure_all(Plan *p, const Reqs &q) {
+    if (q.overflow) return Q2D_EINVAL;
+    for (int r = 0; r < q.n; ++r) {
+        const q2d_status st = ensure(p, *q.r[r].b, q.r[r].bytes);
+        if (st != Q2D_OK) return st;
+    }
+    return Q2D_OK;
+}
+
 q2d_status ensure(Plan *p, Buf &b, size_t bytes) {
+    if (p->arena) return arena_take(*p->arena, b, bytes);
     if (bytes == 0) bytes = 16;
     if (b.bytes >= bytes) return Q2D_OK;
     if (b.p) {
@@ -44,6 +98,40 @@ q2d_status ensure(Plan *p, Buf &b, size_t bytes) {
     }
     b.bytes = sz;
     return Q2D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free step: one static array per device, held
+// until the process ends.  Its host-side name is not a device address: host
+// code uses only the address looked up once per device (with that device
+// current) when a plan is created there.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[Q2D_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_DEVICES = 64;
+std::mutex noalloc_mu;
+bool noalloc_looked[NOALLOC_DEVICES];
+char *noalloc_ptr[NOALLOC_DEVICES];
+}  // namespace
+
+// once per device, with that device current (plan creation)
+static void noalloc_setup(int dev) {
+    if (dev < 0 || dev >= NOALLOC_DEVICES) return;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_looked[dev]) return;
+    noalloc_looked[dev] = true;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr)
+        noalloc_ptr[dev] = (char *)ptr;
+    else
+        (void)hipGetLastError();
+}
+
+static char *noalloc_base(int dev) {
+    if (dev < 0 || dev >= NOALLOC_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    return noalloc_ptr[dev];
 }
 
 int env_int(const char *name, int dflt) {
@@ -335,6 +423,7 @@ q2d_status plan_init(Plan *p, double Lx, double Ly, double Lz, double alpha, dou
     p->stream = (hipStream_t)stream;
     p->serial = env_int("Q2D_SERIAL", 0) != 0;
     if (hipGetDevice(&p->device) != hipSuccess) return Q2D_EDEVICE;
+    noalloc_setup(p->device);
     if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_sorted, hipEventDisableTiming) != hipSuccess ||
@@ -678,6 +767,48 @@ q2d_status q2d_rbm_step(q2d_plan_t p, const void *pos, const void *q, int64_t N,
     const q2d_status st = check_rbm(p, pos, q, N, P);
     if (st != Q2D_OK) return st;
     return rbm_step_body(p, pos, q, N, P, seed, step, phi, F, E, modes_out);
+}
+
+// The allocation-free step: the same body with every scratch buffer of the
+// call lent from the device's static array.  The requests are listed in the
+// order the body ensures them (sampler, sort, inverse permutation and k = 0 on
+// the internal stream, k != 0 passes, epilogue), so arena_need() is the exact
+// number of bytes the call takes.
+q2d_status q2d_rbm_step_noalloc(q2d_plan_t p, const void *pos, const void *q, int64_t N,
+                                int32_t P, uint64_t seed, uint64_t step, void *phi, void *F,
+                                double *E, int32_t *modes_out) {
+    q2d_status st = check_rbm(p, pos, q, N, P);
+    if (st != Q2D_OK) return st;
+    char *base = noalloc_base(p->device);
+    if (!base) return Q2D_EDEVICE;
+    Reqs req;
+    sampler_reqs(p, P, req);
+    if (N > 0) {
+        sort_reqs(p, N, req);
+        inv_reqs(p, N, req);
+        k0_reqs(p, N, req);
+        kmodes_reqs(p, N, P, req);
+        epilogue_reqs(p, N, req);
+    }
+    if (arena_need(req) > Q2D_NOALLOC_SCRATCH_BYTES) return Q2D_ECAPACITY;
+    Arena a;
+    a.base = base;
+    a.cap = Q2D_NOALLOC_SCRATCH_BYTES;
+    // timing events are not created inside this call
+    const int timing = p->timing;
+    p->timing = 0;
+    p->arena = &a;
+    st = rbm_step_body(p, pos, q, N, P, seed, step, phi, F, E, modes_out);
+    p->arena = nullptr;
+    p->timing = timing;
+    arena_restore(a);
+    if (st != Q2D_OK) {
+        // work already enqueued on the internal stream ends before the
+        // caller's stream goes on (the next call reuses the same memory)
+        if (hipEventRecord(p->ev_k0, p->side) == hipSuccess)
+            (void)hipStreamWaitEvent(p->stream, p->ev_k0, 0);
+    }
+    return st;
 }
 
 q2d_status q2d_long_range_vjp(q2d_plan_t p, const void *pos, const void *q, const void *g,

@@ -168,6 +168,20 @@ __global__ __launch_bounds__(EPI_THREADS) void k_vjp(int64_t N, int nchunks,
 
 }  // namespace
 
+void inv_reqs(Plan *p, int64_t N, Reqs &q) {
+    if (N > 0) q.add(p->inv, (size_t)N * sizeof(int32_t));
+}
+
+// scratch of epilogue() (the inverse permutation only if it is not ready)
+void epilogue_reqs(Plan *p, int64_t N, Reqs &q) {
+    if (N <= 0) return;
+    const int nb = (int)((N + EPI_THREADS - 1) / EPI_THREADS);
+    const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+    q.add(p->epart, (size_t)nb * sizeof(double));
+    q.add(p->outk, (size_t)N * 4 * tsz);
+    inv_reqs(p, N, q);
+}
+
 q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0, void *phi,
                     void *F, double *E) {
     if (N <= 0) {
@@ -214,7 +228,9 @@ q2d_status epilogue(Plan *p, int64_t N, int n_chunks, double diag, bool with_k0,
 
 q2d_status launch_inv(Plan *p, int64_t N) {
     if (N <= 0) return Q2D_OK;
-    q2d_status st = ensure(p, p->inv, (size_t)N * sizeof(int32_t));
+    Reqs req;
+    inv_reqs(p, N, req);
+    q2d_status st = ensure_all(p, req);
     if (st != Q2D_OK) return st;
     k_inv<<<(int)((N + EPI_THREADS - 1) / EPI_THREADS), EPI_THREADS, 0, p->stream>>>(
         p->perm, N, (int32_t *)p->inv.p);

@@ -86,6 +86,42 @@ struct Buf {
     size_t bytes = 0;
 };
 
+// A launcher's scratch needs: the buffers it ensures, in the order it ensures
+// them (fixed capacity: building a list allocates nothing).
+struct BufReq {
+    Buf *b;
+    size_t bytes;
+};
+struct Reqs {
+    static constexpr int CAP = 32;
+    BufReq r[CAP];
+    int n = 0;
+    bool overflow = false;
+    void add(Buf &b, size_t bytes) {
+        if (n < CAP)
+            r[n++] = BufReq{&b, bytes};
+        else
+            overflow = true;
+    }
+};
+
+// Allocation-free calls: while a plan holds an arena, ensure() hands out
+// consecutive 256-byte pieces of it instead of allocating, and remembers the
+// buffer each piece replaced; arena_restore() puts the plan's own buffers back
+// when the call has been enqueued.
+struct Arena {
+    static constexpr int CAP = 48;
+    char *base = nullptr;
+    size_t cap = 0, off = 0;
+    Buf *lent[CAP];
+    Buf saved[CAP];
+    int n = 0;
+};
+// bytes an arena hands out for the requests, in order (the rule of ensure():
+// a buffer already lent with enough bytes is reused, else a new piece)
+size_t arena_need(const Reqs &q);
+void arena_restore(Arena &a);
+
 struct Plan {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -185,10 +221,24 @@ struct Plan {
     double t_ms[5]{};
     int64_t t_cnt[5]{};
     std::vector<hipEvent_t> pend_ev[5];
+    // non-null during an allocation-free call
+    Arena *arena = nullptr;
 };
 
 // growth helper: ensure buffer holds at least `bytes`
 q2d_status ensure(Plan *p, Buf &b, size_t bytes);
+
+// scratch requests of the launchers (the same lists their own ensure() calls use)
+void sort_reqs(Plan *p, int64_t N, Reqs &q);
+void sampler_reqs(Plan *p, int P, Reqs &q);
+void kmodes_reqs(Plan *p, int64_t N, int64_t n_modes, Reqs &q);
+void k0_reqs(Plan *p, int64_t N, Reqs &q);
+void inv_reqs(Plan *p, int64_t N, Reqs &q);
+void epilogue_reqs(Plan *p, int64_t N, Reqs &q);
+// bytes of the range-transfer scratch of a carry scan over ncols columns
+size_t carry_tmp_bytes(int64_t ncols, int nseg);
+// ensure every request of a list
+q2d_status ensure_all(Plan *p, const Reqs &q);
 
 // plan set-up shared by single systems and replica batches (q2d_api.hip)
 q2d_status plan_init(Plan *p, double Lx, double Ly, double Lz, double alpha, double r_c,

@@ -315,18 +315,26 @@ static q2d_status k0_launch(Plan *p, int64_t N, int nseg, const void *qsrc, doub
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
+void k0_reqs(Plan *p, int64_t N, Reqs &q) {
+    if (N <= 0) return;
+    const int nseg = (int)((N + S0 - 1) / S0);
+    const int mh = p->mh;
+    q.add(p->spans0, (size_t)nseg * mh * 2 * sizeof(cx<double>));
+    q.add(p->agg0, (size_t)2 * nseg * (mh + 1) * 2 * sizeof(cx<double>));
+    q.add(p->phi0, (size_t)N * sizeof(double));
+    q.add(p->fz0, (size_t)N * sizeof(double));
+    q.add(p->carry_tmp0, carry_tmp_bytes((int64_t)(mh + 1) * 2, nseg));
+}
+
 q2d_status k0_run(Plan *p, int64_t N) {
     if (N <= 0) return Q2D_OK;
     tstart(p, 3);
     const int nseg = (int)((N + S0 - 1) / S0);
     const int mh = p->mh;
     q2d_status st;
-    if ((st = ensure(p, p->spans0, (size_t)nseg * mh * 2 * sizeof(cx<double>))) != Q2D_OK)
-        return st;
-    if ((st = ensure(p, p->agg0, (size_t)2 * nseg * (mh + 1) * 2 * sizeof(cx<double>))) != Q2D_OK)
-        return st;
-    if ((st = ensure(p, p->phi0, (size_t)N * sizeof(double))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->fz0, (size_t)N * sizeof(double))) != Q2D_OK) return st;
+    Reqs req;
+    k0_reqs(p, N, req);
+    if ((st = ensure_all(p, req)) != Q2D_OK) return st;
     if ((st = spans_k0(p, nseg, S0, N)) != Q2D_OK) return st;
     const void *qsrc = p->src ? p->src : p->s_q.p;
     const double PI = 3.14159265358979323846;

@@ -314,15 +314,26 @@ q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
+void sampler_reqs(Plan *p, int P, Reqs &q) {
+    const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
+    const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
+    if (p->opts.sampler != Q2D_SAMPLER_IID) {
+        const int D = p->opts.thin > 0 ? p->opts.thin : 1;
+        const int n = SAMPLER_RESERVE + P * D;
+        q.add(p->rb_work, (size_t)n * (2 * sizeof(int32_t) + 2 * sizeof(double)));
+    }
+    q.add(p->rb_modes, (size_t)2 * p_pad * sizeof(int32_t));
+    q.add(p->rb_coef, (size_t)coef_fields(p->mh) * p_pad * tsz);
+}
+
 q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step) {
     const double PI = 3.14159265358979323846;
+    Reqs req;
+    sampler_reqs(p, P, req);
+    q2d_status st;
+    if ((st = ensure_all(p, req)) != Q2D_OK) return st;
     if (p->opts.sampler == Q2D_SAMPLER_IID) {
         const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
-        q2d_status st;
-        if ((st = ensure(p, p->rb_modes, (size_t)2 * p_pad * sizeof(int32_t))) != Q2D_OK) return st;
-        const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
-        if ((st = ensure(p, p->rb_coef, (size_t)coef_fields(p->mh) * p_pad * tsz)) != Q2D_OK)
-            return st;
         k_sample_iid<<<(p_pad + 255) / 256, 256, 0, p->stream>>>(
             P, seed, step, (const double *)p->iid_tab.p, p->iid_mxm, p->iid_mym,
             (int32_t *)p->rb_modes.p, p_pad);
@@ -333,13 +344,6 @@ q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step) {
     const int D = p->opts.thin > 0 ? p->opts.thin : 1;
     const int n = SAMPLER_RESERVE + P * D;
     const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
-    q2d_status st;
-    if ((st = ensure(p, p->rb_work, (size_t)n * (2 * sizeof(int32_t) + 2 * sizeof(double)))) !=
-        Q2D_OK)
-        return st;
-    if ((st = ensure(p, p->rb_modes, (size_t)2 * p_pad * sizeof(int32_t))) != Q2D_OK) return st;
-    const size_t tsz = p->fp32 ? sizeof(float) : sizeof(double);
-    if ((st = ensure(p, p->rb_coef, (size_t)coef_fields(p->mh) * p_pad * tsz)) != Q2D_OK) return st;
     int32_t *prop = (int32_t *)p->rb_work.p;
     double *wgt = (double *)((char *)p->rb_work.p + (size_t)n * 2 * sizeof(int32_t));
     double *uacc = wgt + n;

@@ -1073,10 +1073,19 @@ __global__ __launch_bounds__(256) void k_capply(const CArgs<T> a, int nr, const 
     walk2<T, KMODE, true>(a, dc, col, s0, s1, c, D);
 }
 
+}  // namespace
+
+size_t carry_tmp_bytes(int64_t ncols, int nseg) {
+    const int64_t nr = (nseg + CAR_L - 1) / CAR_L;
+    return (size_t)2 * ncols * nr * 2 * sizeof(cx<double>);
+}
+
+namespace {
+
 template <typename T, bool KMODE>
 q2d_status carry_run(Plan *p, const CArgs<T> &ca, Buf &tmp) {
     const int nr = (ca.nseg + CAR_L - 1) / CAR_L;
-    q2d_status st = ensure(p, tmp, (size_t)2 * ca.ncols * nr * 2 * sizeof(cx<double>));
+    q2d_status st = ensure(p, tmp, carry_tmp_bytes(ca.ncols, ca.nseg));
     if (st != Q2D_OK) return st;
     cx<double> *rc = (cx<double> *)tmp.p;
     const int64_t nt = (int64_t)ca.ncols * nr;
@@ -1212,57 +1221,82 @@ int choose_S(int64_t N) {
 // Output chunks: one per unit and direction when each direction has its own
 // work-groups (the default), else one per unit; later mode batches add into
 // the F = 1 units' chunks.
+struct KLayout {
+    int S, nseg;
+    int64_t MB, nfull, gpad_max;
+    int rem, rem4, nbatch, ngroups0, gpc, nbands, nch_full, nchunks, nout;
+    bool split;
+};
+
+KLayout kmodes_layout(const Plan *p, int64_t N, int64_t nmodes) {
+    KLayout L{};
+    // a replica batch fixes S: its particles are laid out in whole segments
+    L.S = p->R ? p->S_batch : choose_S(N);
+    L.nseg = (int)((N + L.S - 1) / L.S);
+    L.MB = ((int64_t)std::max(env_int("Q2D_MODE_BATCH", 1024), 1) + WAVE - 1) / WAVE * WAVE;
+    L.nfull = (nmodes / WAVE) * WAVE;
+    L.rem = (int)(nmodes - L.nfull);
+    // a remainder of 61..63 modes rounds up to a whole group: it runs as one
+    // more F = 1 group whose last lanes read the tables' zero-weight padding
+    // (every table is padded to a multiple of 64 columns)
+    if (L.rem > WAVE - SUB) {
+        L.nfull += WAVE;
+        L.rem = 0;
+    }
+    L.rem4 = (L.rem + 3) & ~3;  // band lanes, padded to a multiple of 4
+    L.nbatch = L.nfull > 0 ? (int)((L.nfull + L.MB - 1) / L.MB) : 1;
+    L.ngroups0 = (int)(std::min(L.nfull, L.MB) / WAVE);
+    // groups per unit: enough waves to fill the chip, few output chunks
+    L.gpc = env_int("Q2D_GPC", 0);
+    if (L.gpc <= 0) {
+        const int target = 2048;
+        int nch = (target + L.nseg - 1) / L.nseg;
+        if (nch > L.ngroups0) nch = L.ngroups0;
+        if (nch < 1) nch = 1;
+        L.gpc = L.ngroups0 > 0 ? (L.ngroups0 + nch - 1) / nch : 1;
+    }
+    L.nbands = 0;
+    for (int w = WAVE / 2; w >= SUB; w >>= 1) L.nbands += (L.rem4 & w) ? 1 : 0;
+    if (L.ngroups0 > 0 && (L.ngroups0 + L.gpc - 1) / L.gpc > MAX_UNITS - L.nbands)
+        L.gpc = (L.ngroups0 + MAX_UNITS - L.nbands - 1) / (MAX_UNITS - L.nbands);
+    L.nch_full = L.ngroups0 > 0 ? (L.ngroups0 + L.gpc - 1) / L.gpc : 0;
+    L.nchunks = L.nch_full + L.nbands;
+    // one work-group per direction: twice the waves at half the length, so
+    // the last round of the grid and the slow narrow bands leave a shorter
+    // tail (Q2D_SPLIT=0: both directions in one work-group)
+    L.split = env_int("Q2D_SPLIT", 1) != 0;
+    L.nout = L.split ? 2 * L.nchunks : L.nchunks;
+    L.gpad_max = std::min(L.nfull, L.MB) + L.rem;
+    return L;
+}
+
+template <typename T>
+void kmodes_reqs_t(Plan *p, const KLayout &L, int64_t N, Reqs &q) {
+    const int mh = p->mh;
+    q.add(p->spans, (size_t)L.nseg * mh * 2 * sizeof(cx<double>));
+    q.add(p->agg, (size_t)2 * L.nseg * (mh + 1) * 2 * L.gpad_max * sizeof(cx<T>));
+    q.add(p->outk, (size_t)L.nout * N * 4 * sizeof(T));
+    // the widest mode batch's carry columns
+    q.add(p->carry_tmp, carry_tmp_bytes((int64_t)(mh + 1) * 2 * L.gpad_max, L.nseg));
+}
+
 template <typename T>
 q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coef,
                        int64_t cstride, int64_t moff0, int64_t nmodes, int *nchunks_out) {
     using U = typename Tr<T>::U;
     *nchunks_out = 0;
     if (nmodes <= 0 || N <= 0) return Q2D_OK;
-    // a replica batch fixes S: its particles are laid out in whole segments
-    const int S = p->R ? p->S_batch : choose_S(N);
-    const int nseg = (int)((N + S - 1) / S);
-    const int mh = p->mh;
+    const KLayout L = kmodes_layout(p, N, nmodes);
+    const int S = L.S, nseg = L.nseg, mh = p->mh;
+    const int64_t MB = L.MB, nfull = L.nfull;
+    const int rem = L.rem, rem4 = L.rem4, nbatch = L.nbatch, gpc = L.gpc;
+    const int nch_full = L.nch_full, nchunks = L.nchunks, nout = L.nout;
+    const bool split = L.split;
     const int32_t *seg_rep = p->R ? (const int32_t *)p->seg_rep.p : nullptr;
-    const int64_t MB = ((int64_t)std::max(env_int("Q2D_MODE_BATCH", 1024), 1) + WAVE - 1) / WAVE * WAVE;
-    int64_t nfull = (nmodes / WAVE) * WAVE;
-    int rem = (int)(nmodes - nfull);
-    // a remainder of 61..63 modes rounds up to a whole group: it runs as one
-    // more F = 1 group whose last lanes read the tables' zero-weight padding
-    // (every table is padded to a multiple of 64 columns)
-    if (rem > WAVE - SUB) {
-        nfull += WAVE;
-        rem = 0;
-    }
-    const int rem4 = (rem + 3) & ~3;  // band lanes, padded to a multiple of 4
-    const int nbatch = nfull > 0 ? (int)((nfull + MB - 1) / MB) : 1;
-    const int ngroups0 = (int)(std::min(nfull, MB) / WAVE);
-    // groups per unit: enough waves to fill the chip, few output chunks
-    int gpc = env_int("Q2D_GPC", 0);
-    if (gpc <= 0) {
-        const int target = 2048;
-        int nch = (target + nseg - 1) / nseg;
-        if (nch > ngroups0) nch = ngroups0;
-        if (nch < 1) nch = 1;
-        gpc = ngroups0 > 0 ? (ngroups0 + nch - 1) / nch : 1;
-    }
-    int nbands = 0;
-    for (int w = WAVE / 2; w >= SUB; w >>= 1) nbands += (rem4 & w) ? 1 : 0;
-    if (ngroups0 > 0 && (ngroups0 + gpc - 1) / gpc > MAX_UNITS - nbands)
-        gpc = (ngroups0 + MAX_UNITS - nbands - 1) / (MAX_UNITS - nbands);
-    const int nch_full = ngroups0 > 0 ? (ngroups0 + gpc - 1) / gpc : 0;
-    const int nchunks = nch_full + nbands;
-    // one work-group per direction: twice the waves at half the length, so
-    // the last round of the grid and the slow narrow bands leave a shorter
-    // tail (Q2D_SPLIT=0: both directions in one work-group)
-    const bool split = env_int("Q2D_SPLIT", 1) != 0;
-    const int nout = split ? 2 * nchunks : nchunks;
-    const int64_t gpad_max = std::min(nfull, MB) + rem;
     q2d_status st;
-    if ((st = ensure(p, p->spans, (size_t)nseg * mh * 2 * sizeof(cx<double>))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->agg, (size_t)2 * nseg * (mh + 1) * 2 * gpad_max * sizeof(cx<T>))) !=
-        Q2D_OK)
-        return st;
-    if ((st = ensure(p, p->outk, (size_t)nout * N * 4 * sizeof(T))) != Q2D_OK) return st;
+    Reqs req;
+    kmodes_reqs_t<T>(p, L, N, req);
+    if ((st = ensure_all(p, req)) != Q2D_OK) return st;
     if (!agg_fills_spans<T>(p)) {
         const int64_t n = (int64_t)nseg * mh;
         k_spans<T><<<(int)((n + 255) / 256), 256, 0, p->stream>>>((const T *)p->s_z.p, N, S, nseg,
@@ -1351,6 +1385,15 @@ q2d_status kmodes_impl(Plan *p, int64_t N, const int32_t *modes, const void *coe
 }
 
 }  // namespace
+
+void kmodes_reqs(Plan *p, int64_t N, int64_t n_modes, Reqs &q) {
+    if (n_modes <= 0 || N <= 0) return;
+    const KLayout L = kmodes_layout(p, N, n_modes);
+    if (p->fp32)
+        kmodes_reqs_t<float>(p, L, N, q);
+    else
+        kmodes_reqs_t<double>(p, L, N, q);
+}
 
 q2d_status kmodes_run(Plan *p, int64_t N, const int32_t *modes, const void *coef,
                       int64_t coef_stride, int64_t mode_off, int64_t n_modes, int *n_chunks_out) {

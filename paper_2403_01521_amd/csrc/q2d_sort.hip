@@ -263,23 +263,31 @@ __global__ __launch_bounds__(256) void k_gather1(const T *__restrict__ in,
 }
 
 template <typename T, typename K>
+void sort_reqs_t(Plan *p, int64_t N, Reqs &r) {
+    using U = typename Fix<T>::U;
+    const int ntiles = (int)((N + SORT_TILE - 1) / SORT_TILE);
+    r.add(p->keys_a, N * sizeof(K));
+    r.add(p->keys_b, N * sizeof(K));
+    r.add(p->vals_a, N * sizeof(int32_t));
+    r.add(p->vals_b, N * sizeof(int32_t));
+    r.add(p->hist, ((size_t)256 * ntiles + 256) * sizeof(uint32_t));
+    r.add(p->s_ux, N * sizeof(U));
+    r.add(p->s_uy, N * sizeof(U));
+    r.add(p->s_z, N * sizeof(T));
+    r.add(p->s_q, N * sizeof(T));
+    r.add(p->recs, N * sizeof(Rec<T>));
+}
+
+template <typename T, typename K>
 q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
     const T *pos = (const T *)pos_v;
     const T *q = (const T *)q_v;
     using U = typename Fix<T>::U;
     q2d_status st;
-    if ((st = ensure(p, p->keys_a, N * sizeof(K))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->keys_b, N * sizeof(K))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->vals_a, N * sizeof(int32_t))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->vals_b, N * sizeof(int32_t))) != Q2D_OK) return st;
+    Reqs req;
+    sort_reqs_t<T, K>(p, N, req);
+    if ((st = ensure_all(p, req)) != Q2D_OK) return st;
     const int ntiles = (int)((N + SORT_TILE - 1) / SORT_TILE);
-    if ((st = ensure(p, p->hist, ((size_t)256 * ntiles + 256) * sizeof(uint32_t))) != Q2D_OK)
-        return st;
-    if ((st = ensure(p, p->s_ux, N * sizeof(U))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->s_uy, N * sizeof(U))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->s_z, N * sizeof(T))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->s_q, N * sizeof(T))) != Q2D_OK) return st;
-    if ((st = ensure(p, p->recs, N * sizeof(Rec<T>))) != Q2D_OK) return st;
 
     int *status = (int *)p->status.p;
     double *qsums = (double *)((char *)p->status.p + 16);
@@ -520,6 +528,13 @@ q2d_status radix_sort_u32(Plan *p, int64_t N, int passes, uint32_t **keys_out,
     *keys_out = kin;
     *vals_out = vin;
     return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+void sort_reqs(Plan *p, int64_t N, Reqs &q) {
+    if (p->fp32)
+        sort_reqs_t<float, uint32_t>(p, N, q);
+    else
+        sort_reqs_t<double, uint64_t>(p, N, q);
 }
 
 q2d_status sort_and_stage(Plan *p, const void *pos, const void *q, int64_t N) {
