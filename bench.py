@@ -25,8 +25,12 @@ the K draws), the oracle on all host cores, and the 256-replica batch of
 configuration 5 (aggregate and per-replica evaluations/s, eager and replayed
 as a hipGraph, against one single-system call per replica).
 
+Also: the same workload with the model-reduced M = 10 SOE table (about the
+sup error the Talbot rule needs M = 16 for): its step time and sweep roofline,
+FP32 against FP64 on that table, and its FP64 forces against the M = 16 ones.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
-                       [--no-exact] [--no-replicas]
+                       [--no-exact] [--no-reduced] [--no-replicas]
 """
 
 import argparse
@@ -56,9 +60,25 @@ def flops_per_mode_particle(M):
     return 32 * (M + 1) + 20
 
 
-def soe_table(M):
-    from oracle import soe  # the table is an input of the method; both sides read it
-    return soe.load_table(os.path.join(ROOT, "tests", "golden", "soe_talbot_M%d.txt" % M))
+def soe_table(M, reduced=False):
+    """The SOE table of the run from the library's own host fit: the Talbot
+    rule (the configuration's M = 16 table) or the model-reduced fit."""
+    import paper_2403_01521_amd as q2d
+    w, s, err = q2d.soe_fit_reduced(M) if reduced else q2d.soe_fit(M)
+    return w, s, err
+
+
+def exact_modes(Lx, Ly, alpha, kc):
+    """Every reciprocal vector 0 < |k| <= k_c (full lattice) with its weight
+    (pi/A) e^{-k^2/4 alpha^2}: the exact-k reference list."""
+    mx_max, my_max = int(kc * Lx / (2 * np.pi)), int(kc * Ly / (2 * np.pi))
+    mx, my = np.meshgrid(np.arange(-mx_max, mx_max + 1), np.arange(-my_max, my_max + 1),
+                         indexing="ij")
+    kx, ky = 2 * np.pi * mx / Lx, 2 * np.pi * my / Ly
+    k2 = kx * kx + ky * ky
+    keep = (k2 > 0) & (k2 <= kc * kc)
+    m = np.stack([mx[keep], my[keep]], axis=1).astype(np.int32)
+    return m, np.pi / (Lx * Ly) * np.exp(-k2[keep] / (4 * alpha * alpha))
 
 
 def log(msg):
@@ -213,6 +233,47 @@ def replicas_report(w, s, steps):
             "batch_speedup_vs_sequential": ms_seq / best}
 
 
+def reduced_report(args, box, alpha, N, pos32, q32, sweep_stride, F32_m16):
+    """The same workload and protocol with the model-reduced M = 10 SOE table
+    (q2d_soe_fit_reduced: about the sup error the Talbot rule reaches with
+    M = 16): step time, sweep roofline, FP32 against FP64 on that table, and
+    the FP64 forces of the two tables against each other."""
+    import torch
+    import paper_2403_01521_amd as q2d
+    M = 10
+    log("model-reduced SOE, M = %d" % M)
+    w, s, err = soe_table(M, reduced=True)
+    plan = q2d.Plan(box, alpha, w, s, precision="fp32", n_max=N, p_max=P_MODES)
+    ms = time_steps(plan, pos32, q32, args.steps, args.warmup, 1 << q2d.TIMER_SWEEP,
+                    stride=sweep_stride)
+    sw_ms, sw_cnt = read_timers(plan)["sweep"]
+    _, F32, _, m = plan.rbm_step(pos32, q32, P_MODES, seed=SEED, step=0)
+    torch.cuda.synchronize()
+    plan.close()
+    n_sampled = max(args.steps // sweep_stride, 1)
+    per_step = max(sw_cnt, 1) / n_sampled
+    sweep_ms = sw_ms / max(sw_cnt, 1)
+    fl = flops_per_mode_particle(M) * P_MODES * N
+    achieved = (fl / per_step) / (sweep_ms * 1e-3) / 1e12
+    out = {"M": M, "soe": "model reduction (q2d_soe_fit_reduced), sup error %.2e" % err,
+           "ms_per_step": ms, "value": N / (ms * 1e-3),
+           "sweep_ms": sweep_ms, "sweep_frac": achieved / PEAK_FP32_TFLOPS}
+    if not args.no_fp64:
+        w16, s16, _ = soe_table(M_SOE)
+        pos64, q64 = pos32.double(), q32.double()
+        p64 = q2d.Plan(box, alpha, w, s, precision="fp64", n_max=N, p_max=P_MODES)
+        _, F64, _, m64 = p64.rbm_step(pos64, q64, P_MODES, seed=SEED, step=0)
+        p64.close()
+        p16 = q2d.Plan(box, alpha, w16, s16, precision="fp64", n_max=N, p_max=P_MODES)
+        _, F64_16, _, _ = p16.rbm_step(pos64, q64, P_MODES, seed=SEED, step=0)
+        p16.close()
+        torch.cuda.synchronize()
+        assert np.array_equal(m64.cpu().numpy(), m.cpu().numpy())
+        out["fp32_vs_fp64_force_rel_rms"] = rel(F32.double(), F64)
+        out["fp64_vs_fp64_m16_force_rel_rms"] = rel(F64, F64_16)
+    return out
+
+
 def effective_cores():
     """Cores this process may use: its affinity mask, capped by a cgroup v2/v1
     CPU quota when one is set."""
@@ -280,6 +341,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the FP64 exact-k reference (time and random-batch error)")
+    ap.add_argument("--no-reduced", action="store_true",
+                    help="skip the same step with the model-reduced M = 10 SOE")
     ap.add_argument("--no-replicas", action="store_true",
                     help="skip the 256-replica batch (configuration 5) report")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -298,7 +361,7 @@ def main():
         sys.exit(2)
     import paper_2403_01521_amd as q2d
     import workloads as wl
-    w, s = soe_table(M_SOE)
+    w, s, soe_err = soe_table(M_SOE)
     c32 = wl.make_config(3, dtype=np.float32)
     box, alpha = c32["box"], c32["alpha"]
     N = len(c32["q"])
@@ -346,7 +409,8 @@ def main():
                                "P=100, M=16; FP32 sweeps, segment aggregates on the fp16 "
                                "matrix cores with split (hi+lo) operands, FP64 k=0 term, "
                                "carries and energy",
-                   "N": N, "P": P_MODES, "M": M_SOE, "alpha": alpha, "box": list(box)},
+                   "N": N, "P": P_MODES, "M": M_SOE, "alpha": alpha, "box": list(box),
+                   "soe": "Talbot rule (q2d_soe_fit), sup error %.2e" % soe_err},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": traffic_from_profile(scan_src),
@@ -361,7 +425,6 @@ def main():
     # for the K timed draws (same seeds)
     if not args.no_exact:
         log("FP64 exact-k reference and random-batch error over %d draws" % args.steps)
-        from oracle import soewald2d
         kc = 2 * alpha * np.sqrt(np.log(1e16))
         pos64 = pos32.double()
         q64 = q32.double()
@@ -374,7 +437,7 @@ def main():
         torch.cuda.synchronize()
         t_ex = time.perf_counter() - t0
         # the k != 0 part of the reference force (the j = i constant carries none)
-        m_all, wt_all = soewald2d.exact_modes(box[0], box[1], alpha, kc)
+        m_all, wt_all = exact_modes(box[0], box[1], alpha, kc)
         mh, wh = half_lattice(m_all, wt_all)
         _, F_ref_k, _ = plan_ex.modes_eval(pos64, q64,
                                            torch.tensor(mh, dtype=torch.int32, device="cuda"),
@@ -413,6 +476,8 @@ def main():
     torch.cuda.synchronize()
     r32_modes = m32.cpu().numpy()
     plan32.close()
+    if not args.no_reduced:
+        res["soe_reduced"] = reduced_report(args, box, alpha, N, pos32, q32, sweep_stride, F32)
     if not args.no_fp64:
         log("FP64 random-batch steps")
         pos64 = pos32.double()

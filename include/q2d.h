@@ -283,10 +283,29 @@ q2d_status q2d_plan_check(q2d_plan_t plan);
 q2d_status q2d_soe_fit(int32_t M, double *w, double *s, double *sup_err);
 
 /*
- * q2d_soe_fit_eps -- the same fit with the fewest terms that reaches a
- * prescribed accuracy (Sec. 3: the SOE error eps of eq. SOE1 is the accuracy
- * parameter; Sec. 4.3: M is picked for a tolerance): M = 2, 4, ..., M_max is
- * tried in turn and the first with sup error <= eps is returned in *M, w, s
+ * q2d_soe_fit_reduced -- host FP64 SOE of exp(-x^2) with M terms (M even,
+ * 2 <= M <= Q2D_SOE_REDUCED_MAX) by model reduction, the construction the
+ * paper's own tables (VPMR, Sec. 3 and Sec. 5) come from: the 48-term Talbot
+ * SOE, read as the impulse response of a linear system with poles -s_l, is
+ * reduced by square-root balanced truncation to its M states of largest
+ * Hankel singular value; the reduced poles are the exponents (conjugate
+ * pairs, Re s > 0), the weights follow by least squares, and a Lawson-weighted
+ * Levenberg-Marquardt polish moves the table toward the minimax one.  Sup
+ * errors: about 2e-8 (M = 8), 4e-10 (M = 10), 7e-12 (M = 12), where the Talbot
+ * rule needs M = 16 for 7e-10 (beyond M = 12 the discarded Hankel singular
+ * values reach the FP64 rounding level of the Gramians: use q2d_soe_fit).
+ * Same outputs as q2d_soe_fit; takes up to a few seconds of host time.
+ * Q2D_EUNSUPPORTED if a step fails to converge.
+ */
+#define Q2D_SOE_REDUCED_MAX 12
+q2d_status q2d_soe_fit_reduced(int32_t M, double *w, double *s, double *sup_err);
+
+/*
+ * q2d_soe_fit_eps -- the fewest terms that reach a prescribed accuracy
+ * (Sec. 3: the SOE error eps of eq. SOE1 is the accuracy parameter; Sec. 4.3:
+ * M is picked for a tolerance): M = 2, 4, ..., M_max is tried in turn, each
+ * with the better of q2d_soe_fit_reduced (M <= Q2D_SOE_REDUCED_MAX) and
+ * q2d_soe_fit, and the first with sup error <= eps is returned in *M, w, s
  * (host arrays of at least 2 M_max doubles) and *sup_err (may be NULL).
  * Q2D_ECAPACITY if no M <= M_max reaches eps (w, s, *M then hold the M_max
  * fit); Q2D_EINVAL for eps <= 0 or M_max outside [2, 64].

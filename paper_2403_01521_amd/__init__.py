@@ -44,7 +44,7 @@ EXPORTS = ("q2d_plan_create", "q2d_plan_destroy", "q2d_plan_set_stream", "q2d_pl
            "q2d_batch_check",
            "q2d_plan_check",
            "q2d_slab", "q2d_langevin_step",
-           "q2d_soe_fit", "q2d_soe_fit_eps",
+           "q2d_soe_fit", "q2d_soe_fit_reduced", "q2d_soe_fit_eps",
            "q2d_plan_timing_enable", "q2d_plan_timing_read",
            "q2d_plan_timing_stride",
            "q2d_status_string")
@@ -100,6 +100,7 @@ def load_library(path=None):
     lib.q2d_langevin_step.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, dbl, dbl, dbl, u64, u64,
                                       i32]
     lib.q2d_soe_fit.argtypes = [i32, dp, dp, dp]
+    lib.q2d_soe_fit_reduced.argtypes = [i32, dp, dp, dp]
     lib.q2d_soe_fit_eps.argtypes = [dbl, i32, ctypes.POINTER(ctypes.c_int32), dp, dp, dp]
     lib.q2d_plan_timing_enable.argtypes = [vp, i32]
     lib.q2d_plan_timing_read.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]
@@ -147,6 +148,19 @@ def soe_fit(M):
     dp = ctypes.POINTER(ctypes.c_double)
     _check(lib.q2d_soe_fit(M, w.ctypes.data_as(dp), s.ctypes.data_as(dp), ctypes.byref(err)),
            "q2d_soe_fit")
+    return w[0::2] + 1j * w[1::2], s[0::2] + 1j * s[1::2], err.value
+
+
+def soe_fit_reduced(M):
+    """Host model-reduced SOE of exp(-x^2) with M terms (balanced truncation of
+    a 48-term Talbot table, then a minimax polish): (w, s, sup_err)."""
+    lib = load_library()
+    w = np.zeros(2 * M)
+    s = np.zeros(2 * M)
+    err = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.q2d_soe_fit_reduced(M, w.ctypes.data_as(dp), s.ctypes.data_as(dp),
+                                   ctypes.byref(err)), "q2d_soe_fit_reduced")
     return w[0::2] + 1j * w[1::2], s[0::2] + 1j * s[1::2], err.value
 
 

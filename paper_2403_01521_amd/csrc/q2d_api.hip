@@ -246,42 +246,6 @@ void lattice_sums(double Lx, double Ly, double alpha, double k_c, const std::vec
     }
 }
 
-struct Fit {
-    std::vector<cd> w, s;
-};
-
-// Midpoint rule on Weideman's optimised Talbot contour
-//   z(t) = n (sigma + mu t cot(a t) + i nu t), t in (-pi, pi),
-// for exp(-x^2) = (1/2 pi i) int e^z sqrt(pi/z) exp(-2 sqrt(z) |x|) dz.
-Fit talbot(int M, double scale) {
-    const double sg = -0.6122, mu = 0.5017, a = 0.6407, nu = 0.2645;
-    const double h = 2.0 * PI / M, n = M * scale;
-    Fit f;
-    for (int j = 0; j < M; ++j) {
-        const double t = -PI + (j + 0.5) * h;
-        const cd z = n * cd(sg + mu * t / std::tan(a * t), nu * t);
-        const double st = std::sin(a * t);
-        const cd dz = n * cd(mu * (1.0 / std::tan(a * t) - a * t / (st * st)), nu);
-        const cd w = h / (2.0 * PI * cd(0, 1)) * std::exp(z) * std::sqrt(PI / z) * dz;
-        f.w.push_back(w);
-        f.s.push_back(2.0 * std::sqrt(z));
-    }
-    return f;
-}
-
-double sup_err(const Fit &f, int npts) {
-    double e = 0.0;
-    for (int i = 0; i <= npts; ++i) {
-        // dense on [0, 12], sparse on [12, 200]
-        const double x = i < npts * 9 / 10 ? 12.0 * i / (npts * 9 / 10)
-                                           : 12.0 + 188.0 * (i - npts * 9 / 10) / (npts / 10);
-        cd v = 0.0;
-        for (size_t l = 0; l < f.w.size(); ++l) v += f.w[l] * std::exp(-f.s[l] * x);
-        e = std::max(e, std::fabs(v.real() - std::exp(-x * x)));
-    }
-    return e;
-}
-
 int first_error(int bits) {
     const int order[] = {Q2D_EOUTOFBOX, Q2D_ENONNEUTRAL, Q2D_ESAMPLER};
     for (int c : order)
@@ -605,43 +569,6 @@ const char *q2d_status_string(q2d_status st) {
         case Q2D_EDTYPE: return "element type differs from the plan's precision";
     }
     return "unknown status";
-}
-
-q2d_status q2d_soe_fit(int32_t M, double *w, double *s, double *sup_error) {
-    if (!w || !s || M < 2 || M > 64 || (M % 2)) return Q2D_EINVAL;
-    Fit best;
-    double be = 1e300;
-    for (int i = 0; i <= 40; ++i) {
-        const double sc = 0.6 + 0.02 * i;
-        Fit f = talbot(M, sc);
-        const double e = sup_err(f, 4000);
-        if (e < be) {
-            be = e;
-            best = f;
-        }
-    }
-    for (int l = 0; l < M; ++l) {
-        w[2 * l] = best.w[l].real();
-        w[2 * l + 1] = best.w[l].imag();
-        s[2 * l] = best.s[l].real();
-        s[2 * l + 1] = best.s[l].imag();
-    }
-    if (sup_error) *sup_error = sup_err(best, 40000);
-    return Q2D_OK;
-}
-
-q2d_status q2d_soe_fit_eps(double eps, int32_t M_max, int32_t *M, double *w, double *s,
-                           double *sup_error) {
-    if (!M || !w || !s || !(eps > 0) || M_max < 2 || M_max > 64) return Q2D_EINVAL;
-    double e = 0.0;
-    for (int m = 2; m <= M_max; m += 2) {
-        const q2d_status st = q2d_soe_fit(m, w, s, &e);
-        if (st != Q2D_OK) return st;
-        *M = m;
-        if (sup_error) *sup_error = e;
-        if (e <= eps) return Q2D_OK;
-    }
-    return Q2D_ECAPACITY;
 }
 
 q2d_status q2d_plan_create(double Lx, double Ly, double Lz, double alpha, double r_c, double k_c,

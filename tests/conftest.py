@@ -17,5 +17,8 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def soe_tables():
     from oracle import soe
-    return {M: soe.load_table(os.path.join(GOLDEN, "soe_talbot_M%d.txt" % M))
-            for M in (8, 12, 16, 20, 24)}
+    t = {M: soe.load_table(os.path.join(GOLDEN, "soe_talbot_M%d.txt" % M))
+         for M in (8, 12, 16, 20, 24)}
+    # model-reduced table (balanced truncation), keyed by name
+    t["r10"] = soe.load_table(os.path.join(GOLDEN, "soe_reduced_M10.txt"))
+    return t

@@ -9,7 +9,9 @@ configuration bench.py times.
 * 8 sampled particles against the direct pair sums (oracle O2);
 * invariants that hold at any size: zero net force, and potential and force
   unchanged under a common shift of x, y (periodic) and z (kept in [0, Lz]);
-* two more draws (other steps, other modes) against O3 on all particles.
+* two more draws (other steps, other modes) against O3 on all particles;
+* one draw with the model-reduced M = 10 SOE table (the accuracy of the
+  M = 16 Talbot table with 6 exponent slots instead of 9) against O3.
 
 Every comparison bounds each particle as well as the norm (tests/_parity.py).
 """
@@ -144,3 +146,29 @@ def test_fullsize_more_draws_vs_recursion_oracle(fullsize, seed, step):
     ep = assert_close(pg, r["phi"], 1e-4, "phi")
     print("draw (%d, %d): F %.3e (per particle %.3e) phi %.3e (%.3e)" % (seed, step, *e, *ep))
     assert abs(float(E.cpu()[0]) - r["U"]) <= 1e-4 * abs(r["U"])
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_reduced_soe_vs_recursion_oracle(soe_tables):
+    """The bench workload with the model-reduced M = 10 table: FP32 on all
+    10^6 particles against O3 (FP64) on the same modes and table."""
+    w, s = soe_tables["r10"]
+    c = wl.make_config(3, dtype=np.float32)
+    box, alpha = c["box"], c["alpha"]
+    N = len(c["q"])
+    print("reduced SOE M = 10, N = %d" % N, flush=True)
+    plan = q2d.Plan(box, alpha, w, s, precision="fp32", n_max=N, p_max=P)
+    phi, F, E, modes = plan.rbm_step(torch.tensor(c["pos"], device="cuda"),
+                                     torch.tensor(c["q"], device="cuda"), P, seed=5, step=77)
+    torch.cuda.synchronize()
+    modes = modes.cpu().numpy()
+    H = lattice.H_direct(box[0], box[1], alpha)
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    r = o3.long_range(c["pos"].astype(np.float64), c["q"].astype(np.float64), box, alpha, w, s,
+                      modes, soewald2d.rb_weights(P, H, box[0], box[1]), include_self_pair=False,
+                      diag=D, nthreads=16)
+    e = assert_close(F.double().cpu().numpy(), r["F"], 1e-4, "F")
+    ep = assert_close(phi.double().cpu().numpy(), r["phi"], 1e-4, "phi")
+    print("reduced SOE: F %.3e (per particle %.3e) phi %.3e (%.3e)" % (*e, *ep))
+    assert abs(float(E.cpu()[0]) - r["U"]) <= 1e-4 * abs(r["U"])
+    plan.close()

@@ -103,6 +103,35 @@ def test_rbm_step_matches_oracle(soe_tables, prec, tol):
     plan.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_rbm_step_reduced_soe(soe_tables, prec, tol):
+    """The random-batch step with the model-reduced M = 10 SOE table (five
+    conjugate pairs: other kernel instantiations than M = 16) against O3."""
+    dtn = np.float32 if prec == "fp32" else np.float64
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    c = wl.make_config(3, dtype=dtn, n_override=20000)
+    w, s = soe_tables["r10"]
+    box, alpha = c["box"], c["alpha"]
+    P = 100
+    plan = q2d.Plan(box, alpha, w, s, precision=prec, n_max=len(c["q"]), p_max=P)
+    phi, F, E, modes = plan.rbm_step(dev(c["pos"], dt), dev(c["q"], dt), P, seed=8, step=5)
+    torch.cuda.synchronize()
+    modes = modes.cpu().numpy()
+    H = lattice.H_direct(box[0], box[1], alpha)
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    assert abs(plan.info()["diag_rb"] - D) < 1e-12 * abs(D)
+    r = o3.long_range(c["pos"], c["q"], box, alpha, w, s, modes,
+                      soewald2d.rb_weights(P, H, box[0], box[1]), include_self_pair=False,
+                      diag=D, nthreads=8)
+    phi = phi.cpu().numpy().astype(np.float64)
+    F = F.cpu().numpy().astype(np.float64)
+    print("rbm reduced SOE", prec, rel(phi, r["phi"]), rel(F, r["F"]))
+    assert_close(phi, r["phi"], tol)
+    assert_close(F, r["F"], tol)
+    assert abs(float(E.cpu()[0]) - r["U"]) < tol * abs(r["U"])
+    plan.close()
+
+
 def test_empty_and_single(soe_tables):
     w, s = soe_tables[16]
     box = (10.0, 10.0, 4.0)

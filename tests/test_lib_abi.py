@@ -85,12 +85,16 @@ def test_host_soe_fit_eps():
     """Accuracy-driven fit: the fewest even M whose sup error reaches eps
     (Sec. 3: eps is the SOE accuracy), checked with the oracle's evaluator."""
     x = np.linspace(0, 8, 20001)
-    for eps, M_expect in ((1e-4, None), (1e-8, None), (1e-12, None)):
+    for eps, M_expect in ((1e-4, 6), (1e-8, 10), (1e-12, None)):
         w, s, M, err = q2d.soe_fit_eps(eps, 64)
         assert err <= eps and M % 2 == 0 and len(w) == M
         assert np.abs(osoe.soe_eval(w, s, x) - np.exp(-x * x)).max() <= 1.01 * eps
+        if M_expect:
+            assert M == M_expect, (eps, M)
         if M > 2:
-            _, _, e_less = q2d.soe_fit(M - 2)
+            e_less = q2d.soe_fit(M - 2)[2]
+            if M - 2 <= 12:
+                e_less = min(e_less, q2d.soe_fit_reduced(M - 2)[2])
             assert e_less > eps
     with pytest.raises(q2d.Q2DError) as ei:
         q2d.soe_fit_eps(1e-30, 8)
@@ -101,6 +105,33 @@ def test_host_soe_fit_eps():
     dp = ctypes.POINTER(ctypes.c_double)
     assert lib.q2d_soe_fit_eps(0.0, 2, ctypes.byref(M), buf.ctypes.data_as(dp),
                                buf.ctypes.data_as(dp), None) == q2d.Q2D_EINVAL
+
+
+@pytest.mark.parametrize("M,bound", [(4, 3e-4), (8, 5e-8), (10, 1e-9), (12, 2e-11)])
+def test_host_soe_fit_reduced(M, bound):
+    """Model-reduced SOE (balanced truncation + minimax polish): its sup error
+    against the Gaussian itself (the oracle's evaluator on a dense grid), the
+    table's structure (conjugate pairs, Re s > 0, no real node), the moments
+    sum w = 1 (value at 0) and sum w / s = sqrt(pi)/2 (integral over the half
+    line) within the sup error's reach, and fewer terms than the Talbot rule
+    for the same accuracy."""
+    w, s, err = q2d.soe_fit_reduced(M)
+    assert len(w) == M and err < bound
+    e_or = osoe.sup_error(w, s, n=40001)
+    assert e_or < bound and abs(e_or - err) <= 1e-3 * err + 1e-15
+    assert np.all(s.real > 0) and np.all(np.abs(s.imag) > 1e-8 * np.abs(s))
+    for l in range(M):
+        d = np.abs(s - np.conj(s[l])) + np.abs(w - np.conj(w[l]))
+        assert d.min() < 1e-12 * (abs(s[l]) + abs(w[l]))
+    assert abs(np.sum(w).real - 1.0) <= 2 * err
+    # the integral of the table over [0, inf) against sqrt(pi)/2 (error bounded
+    # by the sup error times the width where the error lives, ~ 6)
+    assert abs(np.sum(w / s).real - np.sqrt(np.pi) / 2) <= 10 * err
+    if M >= 8:
+        assert q2d.soe_fit(M)[2] > 10 * err
+    with pytest.raises(q2d.Q2DError) as ei:
+        q2d.soe_fit_reduced(14)
+    assert ei.value.code == q2d.Q2D_EINVAL
 
 
 def test_host_rejects_unknown_sampler():
