@@ -29,8 +29,12 @@ Also: the same workload with the model-reduced M = 10 SOE table (about the
 sup error the Talbot rule needs M = 16 for): its step time and sweep roofline,
 FP32 against FP64 on that table, and its FP64 forces against the M = 16 ones.
 
+And a whole force evaluation in the O(N) regime of Sec. 4.1: alpha from
+eq. 59, r_c = 4/alpha, the random-batch long range plus the cell-list real
+space on the same slab.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
-                       [--no-exact] [--no-reduced] [--no-replicas]
+                       [--no-exact] [--no-reduced] [--no-short] [--no-replicas]
 """
 
 import argparse
@@ -186,22 +190,31 @@ def replicas_report(w, s, steps):
     pos = torch.tensor(c["pos"], device="cuda")
     q = torch.tensor(c["q"], device="cuda")
     b = q2d.Batch(boxes, counts, c["alpha"], w, s, precision="fp32", p_max=P)
+    t0 = time.perf_counter()
     S = b.tune(pos, q, P, seed=SEED)
+    tune_s = time.perf_counter() - t0
+    cfg = b.config()
     for i in range(3):
         b.rbm_step(pos, q, P, SEED, 1000 + i)
     torch.cuda.synchronize()
+    # host time to enqueue the steps (the call returns before the GPU is done)
+    # and wall time until they have run
     t0 = time.perf_counter()
     for i in range(steps):
         b.rbm_step(pos, q, P, SEED, i)
+    t1 = time.perf_counter()
     torch.cuda.synchronize()
     ms_eager = (time.perf_counter() - t0) * 1e3 / steps
+    host_eager = (t1 - t0) * 1e3 / steps
     b.capture(pos, q, P, SEED, 0)
     b.replay(3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.replay(steps)
+    t1 = time.perf_counter()
     torch.cuda.synchronize()
     ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+    host_graph = (t1 - t0) * 1e3 / steps
     b.close()
     # the same replicas one call each
     off = np.concatenate([[0], np.cumsum(counts)])
@@ -225,7 +238,10 @@ def replicas_report(w, s, steps):
     per = counts / (best * 1e-3)
     return {"workload": "256 replicas, N log-uniform [1e3, 2e4] (total %d), Lx=Ly=clamp(sqrt(N/0.3),"
                         "30,150), Lz=6, alpha=0.3, P=64, M=16, FP32" % Ntot,
+            "tuned_config": cfg, "tune_s": tune_s,
             "segment": S, "ms_per_step_eager": ms_eager, "ms_per_step_graph": ms_graph,
+            "host_enqueue_ms_per_step_eager": host_eager,
+            "host_enqueue_ms_per_step_graph": host_graph,
             "aggregate_evals_per_s": Ntot / (best * 1e-3),
             "per_replica_evals_per_s": {"min": float(per.min()), "median": float(np.median(per)),
                                         "max": float(per.max())},
@@ -272,6 +288,61 @@ def reduced_report(args, box, alpha, N, pos32, q32, sweep_stride, F32_m16):
         out["fp32_vs_fp64_force_rel_rms"] = rel(F32.double(), F64)
         out["fp64_vs_fp64_m16_force_rel_rms"] = rel(F64, F64_16)
     return out
+
+
+def slab_ball_volume(r, Lz, n=201):
+    """Mean volume of a ball of radius r centred in a slab of height Lz and cut
+    by its walls (centre uniform over the height)."""
+    zs = np.linspace(0.0, Lz, n)
+    vol = []
+    for z in zs:
+        a, b = max(0.0, z - r) - z, min(Lz, z + r) - z
+        vol.append(np.pi * (r * r * (b - a) - (b ** 3 - a ** 3) / 3.0))
+    return float(np.mean(vol))
+
+
+def full_step_report(box, N, pos32, q32, steps):
+    """A whole force evaluation in the O(N) regime of Sec. 4.1: alpha from
+    eq. 59, alpha = (N/V)^{1/3}, r_c = s/alpha with s = 4 (eq. rckc), on the
+    bench slab; q2d_rbm_step (P = 100, M = 16) plus q2d_short_range (cell
+    list), FP32.  Also the real-space sum at the configuration's own
+    alpha = 0.1 (r_c = 40: thousands of neighbours per particle), for scale."""
+    import torch
+    import paper_2403_01521_amd as q2d
+    log("long + short range at the alpha of eq. 59")
+    w, s, _ = soe_table(M_SOE)
+    V = box[0] * box[1] * box[2]
+    rho = N / V
+    alpha = rho ** (1.0 / 3.0)
+    rc = 4.0 / alpha
+    plan = q2d.Plan(box, alpha, w, s, rc=rc, precision="fp32", n_max=N, p_max=P_MODES)
+
+    def timed(fn, n):
+        for i in range(3):
+            fn(1000 + i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            fn(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    ms_short = timed(lambda i: plan.short_range(pos32, q32), steps)
+    ms_long = timed(lambda i: plan.rbm_step(pos32, q32, P_MODES, seed=SEED, step=i), steps)
+    ms_step = timed(lambda i: (plan.rbm_step(pos32, q32, P_MODES, seed=SEED, step=i),
+                               plan.short_range(pos32, q32)), steps)
+    plan.close()
+    rc1 = 40.0
+    plan1 = q2d.Plan(box, 0.1, w, s, rc=rc1, precision="fp32", n_max=N, p_max=1)
+    ms_short1 = timed(lambda i: plan1.short_range(pos32, q32), 3)
+    plan1.close()
+    return {"alpha": alpha, "r_c": rc, "s": 4.0,
+            "neighbours_per_particle": rho * slab_ball_volume(rc, box[2]),
+            "short_ms": ms_short, "long_rbm_ms": ms_long, "step_ms": ms_step,
+            "step_evals_per_s": N / (ms_step * 1e-3),
+            "short_ms_at_alpha_0.1_rc_40": ms_short1,
+            "note": "alpha = (N/V)^(1/3) (eq. 59), r_c = 4/alpha (eq. rckc); FP32; "
+                    "step = q2d_rbm_step (P=100, M=16) + q2d_short_range"}
 
 
 def effective_cores():
@@ -343,6 +414,8 @@ def main():
                     help="skip the FP64 exact-k reference (time and random-batch error)")
     ap.add_argument("--no-reduced", action="store_true",
                     help="skip the same step with the model-reduced M = 10 SOE")
+    ap.add_argument("--no-short", action="store_true",
+                    help="skip the long + short range step at the alpha of eq. 59")
     ap.add_argument("--no-replicas", action="store_true",
                     help="skip the 256-replica batch (configuration 5) report")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -478,6 +551,9 @@ def main():
     plan32.close()
     if not args.no_reduced:
         res["soe_reduced"] = reduced_report(args, box, alpha, N, pos32, q32, sweep_stride, F32)
+    if not args.no_short:
+        res["long_plus_short_eq59"] = full_step_report(box, N, pos32, q32,
+                                                       max(10, args.steps // 5))
     if not args.no_fp64:
         log("FP64 random-batch steps")
         pos64 = pos32.double()

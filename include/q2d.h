@@ -351,16 +351,26 @@ q2d_status q2d_plan_timing_stride(q2d_plan_t plan, int32_t n);
  *   Each replica's result is the single-system q2d_rbm_step result for its
  *   box and seed_r (Alg. 2, Fourier part).
  * q2d_batch_set_segment: segment length S (multiple of 64 in [64, 512]) of
- *   the replicas' layout; q2d_batch_tune times S = 64, 128, 256, 512 on the
- *   caller's data (a few steps each; phi, F, E serve as scratch), keeps the
- *   fastest and returns it in *segment.
+ *   the replicas' layout.
+ * q2d_batch_set_config / q2d_batch_get_config: the launch shapes of a step --
+ *   segment length S; split = 1 (each sweep direction in its own work-groups)
+ *   or 2 (both directions in one); agg_cpw = 1, 2 or 4 (16-mode chunks per
+ *   wave of the FP32 aggregate pass).  Results do not depend on them beyond
+ *   rounding.  Q2D_EINVAL for other values.
+ * q2d_batch_tune: picks the launch shapes by timing candidates on the
+ *   caller's data (phi, F, E serve as scratch; one untimed and 3 timed steps
+ *   each), by coordinate descent: S over 64, 128, 256, 512, then split, then
+ *   agg_cpw, then S again; keeps the fastest, returns its S in *segment, and
+ *   caches the choice for the process by (device, R, total N, P, M,
+ *   precision): a later tune of the same shape applies it without timing.
  * q2d_batch_capture: runs one step eagerly (step0), then captures one step
  *   into a hipGraph on the batch's internal stream; the graph reads its step
  *   number from device memory (starting at step0) and increments it last, so
  *   q2d_batch_replay(n) enqueues n steps step0, step0 + 1, ... on the batch's
  *   stream reading pos, q and writing phi, F, E at the captured addresses
- *   (keep them alive; update pos in place between replays).  A new layout
- *   (set_segment, tune) drops the graph (replay then returns Q2D_EUNSUPPORTED).
+ *   (keep them alive; update pos in place between replays).  A new layout or
+ *   launch shape (set_segment, set_config, tune) drops the graph (replay then
+ *   returns Q2D_EUNSUPPORTED).
  * q2d_batch_info: current S, padded particle count, and host copies of H_r
  *   and the random-batch j = i constants (arrays of R, or NULL).
  * q2d_batch_check: as q2d_plan_check.
@@ -372,6 +382,8 @@ q2d_status q2d_batch_create(int32_t R, const double *boxes, const int64_t *n, do
 q2d_status q2d_batch_destroy(q2d_batch_t batch);
 q2d_status q2d_batch_set_stream(q2d_batch_t batch, void *stream);
 q2d_status q2d_batch_set_segment(q2d_batch_t batch, int32_t S);
+q2d_status q2d_batch_set_config(q2d_batch_t batch, int32_t S, int32_t split, int32_t agg_cpw);
+q2d_status q2d_batch_get_config(q2d_batch_t batch, int32_t *S, int32_t *split, int32_t *agg_cpw);
 q2d_status q2d_batch_info(q2d_batch_t batch, int32_t *segment, int64_t *n_padded, double *H,
                           double *diag_rb);
 q2d_status q2d_batch_rbm_step(q2d_batch_t batch, const void *pos, const void *q, int32_t P,

@@ -39,7 +39,8 @@ EXPORTS = ("q2d_plan_create", "q2d_plan_destroy", "q2d_plan_set_stream", "q2d_pl
            "q2d_long_range", "q2d_rbm_step", "q2d_rbm_step_noalloc", "q2d_long_range_vjp",
            "q2d_rbm_step_vjp",
            "q2d_modes_eval", "q2d_short_range", "q2d_batch_create", "q2d_batch_destroy",
-           "q2d_batch_set_stream", "q2d_batch_set_segment", "q2d_batch_info",
+           "q2d_batch_set_stream", "q2d_batch_set_segment", "q2d_batch_set_config",
+           "q2d_batch_get_config", "q2d_batch_info",
            "q2d_batch_rbm_step", "q2d_batch_tune", "q2d_batch_capture", "q2d_batch_replay",
            "q2d_batch_check",
            "q2d_plan_check",
@@ -112,6 +113,8 @@ def load_library(path=None):
     lib.q2d_batch_destroy.argtypes = [vp]
     lib.q2d_batch_set_stream.argtypes = [vp, vp]
     lib.q2d_batch_set_segment.argtypes = [vp, i32]
+    lib.q2d_batch_set_config.argtypes = [vp, i32, i32, i32]
+    lib.q2d_batch_get_config.argtypes = [vp, i32p, i32p, i32p]
     lib.q2d_batch_info.argtypes = [vp, i32p, i64p, dp, dp]
     lib.q2d_batch_rbm_step.argtypes = [vp, vp, vp, i32, u64, u64, vp, vp, vp, vp]
     lib.q2d_batch_tune.argtypes = [vp, vp, vp, i32, u64, vp, vp, vp, i32p]
@@ -531,8 +534,22 @@ class Batch:
     def set_segment(self, S):
         _check(self._lib.q2d_batch_set_segment(self._h, int(S)), "q2d_batch_set_segment")
 
+    def set_config(self, S, split, agg_cpw):
+        """Launch shapes: segment length S, split (1: one work-group per sweep
+        direction, 2: both in one), agg_cpw (16-mode chunks per wave, 1/2/4)."""
+        _check(self._lib.q2d_batch_set_config(self._h, int(S), int(split), int(agg_cpw)),
+               "q2d_batch_set_config")
+
+    def config(self):
+        S, sp, cw = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(self._lib.q2d_batch_get_config(self._h, ctypes.byref(S), ctypes.byref(sp),
+                                              ctypes.byref(cw)), "q2d_batch_get_config")
+        return dict(segment=S.value, split=sp.value, agg_cpw=cw.value)
+
     def tune(self, pos, q, P, seed=0):
-        """Time the segment lengths on these inputs, keep the fastest, return it."""
+        """Tune the launch shapes on these inputs (segment length, sweep split,
+        aggregate chunks per wave); keeps the fastest and returns its segment
+        length (the whole choice: config())."""
         self._sync_stream()
         pos, q, phi, F, E = self._io(pos, q)
         seg = ctypes.c_int32(0)

@@ -11,10 +11,12 @@
 //
 // A step can be captured in a hipGraph whose sampler reads the step number
 // from device memory and whose last node increments it, so replays advance
-// the random batch like successive calls.  The segment length is tuned by
-// timing the candidates on the caller's data.
+// the random batch like successive calls.  The launch shapes (segment
+// length, sweep work-group split, aggregate chunks per wave) are tuned by
+// timing candidates on the caller's data.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -38,6 +40,49 @@ __global__ void k_batch_modes_out(const int32_t *modes, int R, int P, int p_pad,
 }
 
 bool valid_S(int S) { return S >= WAVE && S <= 512 && S % WAVE == 0; }
+
+// launch shapes of a batch step (segment length, sweep split, aggregate
+// chunks per wave; see Plan::cfg_split / cfg_cpw)
+struct Config {
+    int S, split, cpw;
+};
+
+bool valid_config(int S, int split, int cpw) {
+    return valid_S(S) && (split == 1 || split == 2) && (cpw == 1 || cpw == 2 || cpw == 4);
+}
+
+// shapes a tune has chosen, per process
+struct TuneKey {
+    int device, R;
+    int64_t ntot;
+    int P, M, fp32;
+    bool operator==(const TuneKey &o) const {
+        return device == o.device && R == o.R && ntot == o.ntot && P == o.P && M == o.M &&
+               fp32 == o.fp32;
+    }
+};
+std::mutex tune_mu;
+std::vector<std::pair<TuneKey, Config>> tune_cache;
+
+bool tune_cache_get(const TuneKey &k, Config &c) {
+    std::lock_guard<std::mutex> lock(tune_mu);
+    for (const auto &e : tune_cache)
+        if (e.first == k) {
+            c = e.second;
+            return true;
+        }
+    return false;
+}
+
+void tune_cache_put(const TuneKey &k, const Config &c) {
+    std::lock_guard<std::mutex> lock(tune_mu);
+    for (auto &e : tune_cache)
+        if (e.first == k) {
+            e.second = c;
+            return;
+        }
+    tune_cache.push_back({k, c});
+}
 
 // padded offsets and the segment -> replica table for segment length S
 q2d_status layout(Plan *p, int S) {
@@ -68,6 +113,26 @@ q2d_status layout(Plan *p, int S) {
     p->graph_exec = nullptr;
     p->graph = nullptr;
     return hipStreamSynchronize(p->stream) == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+Config current_config(const Plan *p) {
+    return Config{p->S_batch, p->cfg_split ? p->cfg_split : 1, p->cfg_cpw ? p->cfg_cpw : 2};
+}
+
+// A new shape: a new layout if S changes; any change drops a captured step
+// (its kernels were recorded with the old shapes)
+q2d_status apply_config(Plan *p, const Config &c) {
+    const Config cur = current_config(p);
+    p->cfg_split = c.split;
+    p->cfg_cpw = c.cpw;
+    if (c.S != cur.S || !p->h_poff.size()) return layout(p, c.S);
+    if (c.split != cur.split || c.cpw != cur.cpw) {
+        if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->graph_exec = nullptr;
+        p->graph = nullptr;
+    }
+    return Q2D_OK;
 }
 
 // One step on p->stream (and the internal stream): sampling || sort, then the
@@ -228,41 +293,95 @@ q2d_status q2d_batch_rbm_step(q2d_batch_t b, const void *pos, const void *q, int
     return batch_step(b, pos, q, P, seed, step, nullptr, phi, F, E, modes_out);
 }
 
+q2d_status q2d_batch_set_config(q2d_batch_t b, int32_t S, int32_t split, int32_t agg_cpw) {
+    if (!b || !valid_config(S, split, agg_cpw)) return Q2D_EINVAL;
+    if (hipSetDevice(b->device) != hipSuccess) return Q2D_EDEVICE;
+    return apply_config(b, Config{S, split, agg_cpw});
+}
+
+q2d_status q2d_batch_get_config(q2d_batch_t b, int32_t *S, int32_t *split, int32_t *agg_cpw) {
+    if (!b) return Q2D_EINVAL;
+    const Config c = current_config(b);
+    if (S) *S = c.S;
+    if (split) *split = c.split;
+    if (agg_cpw) *agg_cpw = c.cpw;
+    return Q2D_OK;
+}
+
+// Coordinate descent over the launch shapes, each candidate timed on the
+// caller's data (one untimed step sizes its scratch, then 3 timed steps):
+// the segment length S in {64, 128, 256, 512}, then the sweep's work-group
+// split {per direction, both directions}, then the aggregate pass's chunks per
+// wave {1, 2, 4}, then S once more.  The result is cached for the process by
+// (device, R, total N, P, M, precision); a later tune of the same shape
+// applies it without timing.
 q2d_status q2d_batch_tune(q2d_batch_t b, const void *pos, const void *q, int32_t P, uint64_t seed,
                           void *phi, void *F, double *E, int32_t *segment) {
     q2d_status st = check_step_args(b, pos, q, P);
     if (st != Q2D_OK) return st;
-    const int cand[] = {64, 128, 256, 512};
+    const TuneKey key{b->device, b->R, b->Ntot, P, b->M, b->fp32 ? 1 : 0};
+    Config best = current_config(b);
+    if (tune_cache_get(key, best)) {
+        if ((st = apply_config(b, best)) == Q2D_OK && segment) *segment = best.S;
+        return st;
+    }
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return Q2D_EDEVICE;
+    if (hipEventCreate(&e0) != hipSuccess) return Q2D_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return Q2D_EDEVICE;
+    }
     const int saved_timing = b->timing;
     b->timing = 0;
-    int best = b->S_batch;
     float best_ms = 1e30f;
-    for (int S : cand) {
-        if ((st = layout(b, S)) != Q2D_OK) break;
-        // one untimed step sizes the scratch for this layout
-        if ((st = batch_step(b, pos, q, P, seed, 0, nullptr, phi, F, E, nullptr)) != Q2D_OK) break;
+    auto time_config = [&](const Config &c) -> q2d_status {
+        q2d_status s2 = apply_config(b, c);
+        if (s2 != Q2D_OK) return s2;
+        if ((s2 = batch_step(b, pos, q, P, seed, 0, nullptr, phi, F, E, nullptr)) != Q2D_OK)
+            return s2;
         (void)hipEventRecord(e0, b->stream);
-        for (int k = 0; k < 3 && st == Q2D_OK; ++k)
-            st = batch_step(b, pos, q, P, seed, 1 + k, nullptr, phi, F, E, nullptr);
+        for (int k = 0; k < 3 && s2 == Q2D_OK; ++k)
+            s2 = batch_step(b, pos, q, P, seed, 1 + k, nullptr, phi, F, E, nullptr);
         (void)hipEventRecord(e1, b->stream);
         float ms = 0.f;
-        if (st != Q2D_OK || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            if (st == Q2D_OK) st = Q2D_EDEVICE;
-            break;
-        }
+        if (s2 != Q2D_OK) return s2;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return Q2D_EDEVICE;
         if (ms < best_ms) {
             best_ms = ms;
-            best = S;
+            best = c;
+        }
+        return Q2D_OK;
+    };
+    const int cand_S[] = {64, 128, 256, 512};
+    const int cand_split[] = {1, 2};
+    const int cand_cpw[] = {1, 2, 4};
+    for (int round = 0; round < 2 && st == Q2D_OK; ++round) {
+        for (int S : cand_S) {
+            Config c = best;
+            c.S = S;
+            if (st == Q2D_OK) st = time_config(c);
+        }
+        if (round == 1) break;
+        for (int sp : cand_split) {
+            Config c = best;
+            c.split = sp;
+            if (st == Q2D_OK) st = time_config(c);
+        }
+        for (int cw : cand_cpw) {
+            Config c = best;
+            c.cpw = cw;
+            if (st == Q2D_OK) st = time_config(c);
         }
     }
     b->timing = saved_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (st == Q2D_OK) st = layout(b, best);
-    if (st == Q2D_OK && segment) *segment = best;
+    if (st == Q2D_OK) st = apply_config(b, best);
+    if (st == Q2D_OK) {
+        tune_cache_put(key, best);
+        if (segment) *segment = best.S;
+    }
     return st;
 }
 

@@ -223,6 +223,10 @@ struct Plan {
     std::vector<hipEvent_t> pend_ev[5];
     // non-null during an allocation-free call
     Arena *arena = nullptr;
+    // launch shapes of the k != 0 passes (0: the default): one work-group per
+    // sweep direction (1) or both in one (2); 16-mode chunks per wave of the
+    // FP32 aggregate pass (1, 2 or 4)
+    int cfg_split = 0, cfg_cpw = 0;
 };
 
 // growth helper: ensure buffer holds at least `bytes`

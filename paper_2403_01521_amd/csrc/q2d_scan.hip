@@ -377,7 +377,8 @@ __device__ inline void split8(const float (&v)[8], h8v &hi, h8v &lo) {
 // chunks of 16 modes (rows: the x and y sources of each chunk).  The
 // beta = k term (mode-dependent decay) stays on the VALU.
 constexpr int AGW_MAX = 8;  // waves per work-group at most
-constexpr int AGG_CPW = 2;  // 16-mode chunks per wave (measured best of 1, 2, 4)
+constexpr int AGG_CPW = 2;  // default 16-mode chunks per wave (measured best of 1, 2, 4 at
+                            // the single-system bench size; replica batches tune it)
 
 // the FP64 betas and the spans table (W, G per (segment, pair)) that the
 // aggregate kernel fills for the carry scan
@@ -1157,12 +1158,18 @@ void dispatch_sweep(Plan *p, const KArgs<T> &ka, dim3 grid) {
 void dispatch_agg_seg(Plan *p, const KArgs<float> &ka, const SpanArgs &sp) {
     // AGG_CPW chunks of 16 modes per wave, as many waves as that takes (at
     // most AGW_MAX; more chunks take several passes over the segment)
+    const int cpw = p->cfg_cpw ? p->cfg_cpw : AGG_CPW;
     const int nchunk = (ka.nmodes + 15) / 16;
-    const int nw = std::max(1, std::min(AGW_MAX, (nchunk + AGG_CPW - 1) / AGG_CPW));
+    const int nw = std::max(1, std::min(AGW_MAX, (nchunk + cpw - 1) / cpw));
     switch (p->mh) {
-#define Q2D_CASE(n)                                                            \
-    case n:                                                                    \
-        k_agg_seg<n, AGG_CPW><<<ka.nseg, nw * WAVE, 0, p->stream>>>(ka, sp);   \
+#define Q2D_CASE(n)                                                                      \
+    case n:                                                                              \
+        if (cpw == 1)                                                                    \
+            k_agg_seg<n, 1><<<ka.nseg, nw * WAVE, 0, p->stream>>>(ka, sp);               \
+        else if (cpw == 4)                                                               \
+            k_agg_seg<n, 4><<<ka.nseg, nw * WAVE, 0, p->stream>>>(ka, sp);               \
+        else                                                                             \
+            k_agg_seg<n, 2><<<ka.nseg, nw * WAVE, 0, p->stream>>>(ka, sp);               \
         break;
         Q2D_CASE(1) Q2D_CASE(2) Q2D_CASE(3) Q2D_CASE(4) Q2D_CASE(5) Q2D_CASE(6) Q2D_CASE(7)
         Q2D_CASE(8) Q2D_CASE(9) Q2D_CASE(10) Q2D_CASE(11) Q2D_CASE(12)
@@ -1264,7 +1271,7 @@ KLayout kmodes_layout(const Plan *p, int64_t N, int64_t nmodes) {
     // one work-group per direction: twice the waves at half the length, so
     // the last round of the grid and the slow narrow bands leave a shorter
     // tail (Q2D_SPLIT=0: both directions in one work-group)
-    L.split = env_int("Q2D_SPLIT", 1) != 0;
+    L.split = p->cfg_split ? p->cfg_split == 1 : env_int("Q2D_SPLIT", 1) != 0;
     L.nout = L.split ? 2 * L.nchunks : L.nchunks;
     L.gpad_max = std::min(L.nfull, L.MB) + L.rem;
     return L;

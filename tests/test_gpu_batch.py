@@ -4,11 +4,14 @@
   seed (modes bit-exact; FP64 within 1e-12, FP32 within 1e-5), including empty
   and one-particle replicas and boxes with Lx != Ly;
 * one replica against the oracle (O3 with the oracle's own H and j = i
-  constant for that box), FP64 within 1e-10;
-* results independent of the segment length (64 ... 512);
+  constant for that box), FP64 within 1e-10, and two replicas of an FP32
+  batch against O3 directly within 1e-5;
+* results independent of the segment length (64 ... 512) and of the other
+  launch shapes (sweep work-group split, aggregate chunks per wave);
 * a captured step replayed as a hipGraph equals the eager steps it stands
   for, replay after replay (the step number advances on the device);
-* the tuner returns one of the candidates and leaves results unchanged;
+* the tuner returns one of the candidates, leaves results unchanged, and a
+  second tune of the same shape reuses the cached choice;
 * configuration 5 at full size (256 replicas, 1.65e6 particles, P = 64):
   four replicas against single-system plans.
 """
@@ -118,6 +121,67 @@ def test_batch_replica_vs_oracle(soe_tables):
     b.close()
 
 
+def test_batch_fp32_replicas_vs_oracle(soe_tables):
+    """Two replicas of an FP32 batch (a 700- and a 4098-particle box) against
+    O3 in FP64 on the same modes, each with the oracle's own H and j = i
+    constant for its box."""
+    pos, q, boxes, counts = small_batch(np.float32)
+    w, s = soe_tables[16]
+    b = q2d.Batch(boxes, counts, ALPHA, w, s, precision="fp32", p_max=P)
+    phi, F, E, modes = run_batch(b, pos, q, torch.float32, 21, 6)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    for r in (3, 5):
+        sl = slice(off[r], off[r + 1])
+        box = boxes[r]
+        H = lattice.H_direct(box[0], box[1], ALPHA)
+        D = soewald2d.diag_constant(box[0], box[1], ALPHA, w, s)
+        ref = o3.long_range(pos[sl].astype(np.float64), q[sl].astype(np.float64), box, ALPHA,
+                            w, s, modes[r], soewald2d.rb_weights(P, H, box[0], box[1]),
+                            include_self_pair=False, diag=D, nthreads=8)
+        print("fp32 replica %d: F %.2e phi %.2e" % (r, rel(F[sl], ref["F"]),
+                                                    rel(phi[sl], ref["phi"])))
+        assert_close(phi[sl], ref["phi"], 1e-5)
+        assert_close(F[sl], ref["F"], 1e-5)
+        assert abs(E[r] - ref["U"]) < 1e-5 * abs(ref["U"])
+    b.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_batch_launch_shape_invariance(soe_tables, prec, tol):
+    """Every launch shape the tuner may pick gives the same results to
+    rounding (the segment length, the sweep's split, the aggregate pass's
+    chunks per wave): FP64 against the default shape within 1e-12; FP32, whose
+    segmentations round differently, each against the FP64 result within 2e-5
+    (the FP32 rounding bound of a 512-step segment with the SOE weights'
+    cancellation is about 3e-5; observed up to 1.1e-5 on these mixed small
+    replicas)."""
+    dtn = np.float32 if prec == "fp32" else np.float64
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    pos, q, boxes, counts = small_batch(dtn)
+    w, s = soe_tables[16]
+    b = q2d.Batch(boxes, counts, ALPHA, w, s, precision=prec, p_max=P)
+    assert b.config() == {"segment": 256, "split": 1, "agg_cpw": 2}
+    if prec == "fp64":
+        ref = run_batch(b, pos, q, dt, 4, 2)
+    else:
+        b64 = q2d.Batch(boxes, counts, ALPHA, w, s, precision="fp64", p_max=P)
+        ref = run_batch(b64, pos.astype(np.float64), q.astype(np.float64), torch.float64, 4, 2)
+        b64.close()
+    for S, split, cpw in ((256, 2, 1), (128, 1, 4), (512, 2, 2), (64, 1, 1)):
+        b.set_config(S, split, cpw)
+        assert b.config() == {"segment": S, "split": split, "agg_cpw": cpw}
+        out = run_batch(b, pos, q, dt, 4, 2)
+        assert np.array_equal(out[3], ref[3])
+        print(prec, (S, split, cpw), "phi %.2e F %.2e" % (rel(out[0], ref[0]), rel(out[1], ref[1])))
+        assert_close(out[0], ref[0], tol, (S, split, cpw))
+        assert_close(out[1], ref[1], tol, (S, split, cpw))
+    for bad in ((100, 1, 2), (256, 3, 2), (256, 1, 3)):
+        with pytest.raises(q2d.Q2DError) as ei:
+            b.set_config(*bad)
+        assert ei.value.code == q2d.Q2D_EINVAL
+    b.close()
+
+
 def test_batch_segment_length_invariance(soe_tables):
     pos, q, boxes, counts = small_batch(np.float64)
     w, s = soe_tables[16]
@@ -165,11 +229,19 @@ def test_batch_tune(soe_tables):
     b = q2d.Batch(boxes, counts, ALPHA, w, s, precision="fp32", p_max=P)
     ref = run_batch(b, pos, q, torch.float32, 1, 1)
     S = b.tune(dev(pos, torch.float32), dev(q, torch.float32), P, seed=1)
-    assert S in (64, 128, 256, 512) and b.info()["segment"] == S
+    cfg = b.config()
+    assert S in (64, 128, 256, 512) and b.info()["segment"] == S == cfg["segment"]
+    assert cfg["split"] in (1, 2) and cfg["agg_cpw"] in (1, 2, 4)
     out = run_batch(b, pos, q, torch.float32, 1, 1)
     assert np.array_equal(out[3], ref[3])
     assert_close(out[1], ref[1], 1e-5)
     b.close()
+    # a new batch of the same shape: the tune applies the cached choice
+    b2 = q2d.Batch(boxes, counts, ALPHA, w, s, precision="fp32", p_max=P)
+    b2.set_config(64, 2, 4 if cfg["agg_cpw"] != 4 else 1)
+    assert b2.tune(dev(pos, torch.float32), dev(q, torch.float32), P, seed=1) == S
+    assert b2.config() == cfg
+    b2.close()
 
 
 def test_batch_config5_fullsize(soe_tables):

@@ -69,6 +69,28 @@ def test_short_range_many_cells(soe_tables, prec, tol):
     assert np.abs(F.sum(0)).max() < 50 * tol * np.sqrt((F * F).sum())
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_short_range_eq59_alpha(soe_tables, prec, tol):
+    """10^5 charges at the bench slab's density (0.278 per unit volume, box
+    190 x 190 x 10) with alpha from eq. 59, alpha = (N/V)^{1/3}, and
+    r_c = s/alpha with s = 4 (eq. rckc): about 200 neighbours per particle, the
+    O(N) regime of the real-space sum.  100 sampled particles against the
+    oracle's erfc sum; zero net force over the whole box."""
+    box = (190.0, 190.0, 10.0)
+    N = 100000
+    pos, q = wl.random_system(N, box, seed=59, dtype=np.float32 if prec == "fp32"
+                              else np.float64)
+    alpha = (N / (box[0] * box[1] * box[2])) ** (1.0 / 3.0)
+    rc = 4.0 / alpha
+    w, s = soe_tables[8]
+    phi, F, E = short(box, alpha, rc, w, s, pos, q, prec)
+    tg = np.random.default_rng(3).choice(N, 100, replace=False)
+    rphi, rF = ewald2d.real_space(pos, q, box, alpha, rc, targets=tg)
+    print("short eq.59 alpha=%.4f rc=%.3f" % (alpha, rc), prec,
+          assert_close(phi[tg], rphi, tol), assert_close(F[tg], rF, tol))
+    assert np.abs(F.sum(0)).max() < 50 * tol * np.sqrt((F * F).sum())
+
+
 def test_config1_long_plus_short(soe_tables):
     """Configuration 1's outputs (total energy, per-particle potential and
     forces) as long + short range on the GPU, FP64: against the SOE oracle
