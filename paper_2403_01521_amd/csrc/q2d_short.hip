@@ -17,14 +17,17 @@
 //    per range.  r_c <= min(Lx, Ly)/2 (checked at plan creation) puts at most
 //    one image of a pair within r_c, so ranges that repeat a column with
 //    another shift add nothing twice;
-//  * candidates are loaded 64 at a time, one per lane, and broadcast with
-//    readlane: every lane first builds a bit mask of the candidates within r_c
-//    of its target, then evaluates only those pairs (lanes fetch their own
-//    candidate with a lane permute), so the erfc work is not paid for the
-//    ~60% of candidates outside the sphere;
+//  * candidates are staged 64 at a time (one coalesced record per lane, the
+//    periodic shift applied) in a per-wave LDS buffer of SR_BUF records; per
+//    block of 64 staged candidates every lane builds a bit mask of those within
+//    r_c of its target (broadcast LDS reads), then evaluates only those pairs,
+//    one per round, reading its own candidate from LDS: the erfc work is not
+//    paid for the ~80% of candidates outside the sphere;
 //  * FP32 plans: erfc(x) = erfcx(x) e^{-x^2}, with erfcx as a Chebyshev series
-//    in u = 1/(1 + x/2) on [0, alpha r_c] fitted in FP64 at each call from the
-//    definition (relative error below 1e-9 for alpha r_c <= 8) and e^{-x^2}
+//    of degree 9 in u = 1/(1 + x/2) on [0, alpha r_c] fitted in FP64 at each
+//    call from the definition (relative error below 1e-7 for alpha r_c <= 8,
+//    the size of FP32 rounding; degree 12 reached 2e-10 and cost 3 more FMAs
+//    per pair) and e^{-x^2}
 //    shared with the force term; FP64 plans call the library erfc.  Each
 //    chunk's pair terms are summed in the plan's precision and added to FP64
 //    accumulators; every target sums its pairs in a fixed order, the energy in
@@ -38,7 +41,8 @@ namespace q2d {
 namespace {
 
 constexpr int SR_WAVES = 4;       // independent waves per work-group
-constexpr int CHEB_DEG = 12;      // degree of the erfcx series
+constexpr int SR_BUF = 256;       // staged candidates per wave (LDS records)
+constexpr int CHEB_DEG = 9;       // degree of the erfcx series (FP32 plans)
 
 struct Grid {
     int nx, ny, nz;
@@ -122,15 +126,6 @@ __global__ __launch_bounds__(1024) void k_row_tiles(const int32_t *__restrict__ 
     if (t == 1023) base[ny] = part[1023];
 }
 
-__device__ inline float bcast(float v, int j) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
-}
-__device__ inline double bcast(double v, int j) {
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, j);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), j);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
 
 // erfc(x) and e^{-x^2} for 0 <= x <= alpha r_c
 __device__ inline void erfc_gauss(const ShortArgs &a, float x, float &ec, float &g) {
@@ -153,15 +148,44 @@ __device__ inline void erfc_gauss(const ShortArgs &, double x, double &ec, doubl
 __device__ inline float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ inline double rsq(double v) { return 1.0 / sqrt(v); }
 
+// pair term of one candidate: accumulate q_j erfc(alpha r)/r and the force
+// factor q_j [erfc/r^2 + (2 alpha/sqrt(pi)) e^{-alpha^2 r^2}/r] / r along d
+template <typename T>
+__device__ inline void pair_term(const ShortArgs &a, const Rec4<T> &me, const Rec4<T> &c,
+                                 bool has, T alpha, T c2a, T &sp, T &sfx, T &sfy, T &sfz) {
+    const T dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
+    T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    r2 = has ? r2 : (T)1;
+    const T ri = rsq(r2);
+    T ec, gs;
+    erfc_gauss(a, alpha * (r2 * ri), ec, gs);
+    const T qj = has ? c.q : (T)0;
+    const T er = ec * ri;
+    sp = fma(qj, er, sp);
+    const T fm = qj * fma(c2a, gs, er) * (ri * ri);
+    sfx = fma(fm, dx, sfx);
+    sfy = fma(fm, dy, sfy);
+    sfz = fma(fm, dz, sfz);
+}
+
+// A wave per tile of <= 64 targets (lane = target).  Candidates are staged in
+// a per-wave LDS buffer of SR_BUF records with their periodic shift applied
+// (coalesced loads, one record per lane); when the buffer is full (and at the
+// end) it is processed block by block: every lane builds its in-range bit mask
+// over 64 candidates from broadcast LDS reads, then walks its own candidates,
+// one per round, reading each from LDS (no lane permutes, no readlane chains).
+// Each lane sums its pairs in a fixed order (deterministic).
 template <typename T>
 __global__ __launch_bounds__(SR_WAVES *WAVE) void k_short_tiles(
     const ShortArgs a, const Rec4<T> *__restrict__ srec, const uint32_t *__restrict__ skey,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ start,
     const int32_t *__restrict__ row_base, T *__restrict__ phi, T *__restrict__ F,
     double *__restrict__ tile_e) {
+    __shared__ Rec4<T> buf_all[SR_WAVES][SR_BUF];
     const Grid &g = a.g;
-    const int lane = threadIdx.x % WAVE;
-    const int tile = blockIdx.x * SR_WAVES + (int)(threadIdx.x / WAVE);
+    const int lane = threadIdx.x % WAVE, wv = (int)(threadIdx.x / WAVE);
+    Rec4<T> *buf = buf_all[wv];
+    const int tile = blockIdx.x * SR_WAVES + wv;
     if (tile >= a.ntile_max) return;
     const int ntiles = row_base[g.ny];
     if (tile >= ntiles) {
@@ -202,55 +226,60 @@ __global__ __launch_bounds__(SR_WAVES *WAVE) void k_short_tiles(
     const T alpha = (T)a.alpha;
     const T c2a = (T)(2.0 * a.alpha / 1.7724538509055160273);
     double aphi = 0.0, afx = 0.0, afy = 0.0, afz = 0.0;
+    int fill = 0;  // staged candidates (wave-uniform)
 
-    // one range of candidates [b, e) seen through the periodic shift (sx, sy)
-    auto range = [&](int b, int e, T sx, T sy) {
-        for (int c0 = b; c0 < e; c0 += WAVE) {
-            const int nc = min(WAVE, e - c0);
-            const Rec4<T> cd = srec[c0 + (lane < nc ? lane : 0)];
-            const T cxp = cd.x + sx, cyp = cd.y + sy, czp = cd.z, cq = cd.q;
-            // in-range mask of this lane's target over the nc candidates
+    // the staged candidates [0, fill), one block of 64 at a time: this lane's
+    // in-range mask over the block (broadcast LDS reads), then its pairs, one
+    // per round, each candidate read from LDS
+    auto flush = [&]() {
+        // (the wave's LDS accesses run in program order: the staged records
+        // of every lane are in place for the reads below)
+        __builtin_amdgcn_wave_barrier();
+        T sp = 0, sfx = 0, sfy = 0, sfz = 0;
+        for (int b0 = 0; b0 < fill; b0 += WAVE) {
+            const Rec4<T> *blk = buf + b0;
+            const int nb = min(WAVE, fill - b0);
             uint32_t mlo = 0, mhi = 0;
-            for (int j = 0; j < nc; ++j) {
-                const T dx = me.x - bcast(cxp, j), dy = me.y - bcast(cyp, j),
-                        dz = me.z - bcast(czp, j);
+            for (int j = 0; j < nb; ++j) {
+                const Rec4<T> c = blk[j];  // same address on every lane
+                const T dx = me.x - c.x, dy = me.y - c.y, dz = me.z - c.z;
                 const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                const bool in = r2 < rc2 && r2 > (T)0;
+                const uint32_t bit = (r2 < rc2 && r2 > (T)0) ? 1u : 0u;
                 if (j < 32)
-                    mlo |= in ? (1u << j) : 0u;
+                    mlo |= bit << j;
                 else
-                    mhi |= in ? (1u << (j - 32)) : 0u;
+                    mhi |= bit << (j - 32);
             }
             if (!valid) mlo = mhi = 0;
-            // the pairs: every lane takes its next candidate each round
-            T sp = 0, sfx = 0, sfy = 0, sfz = 0;
-            while (__any(mlo | mhi)) {
+            while (__any((mlo | mhi) != 0)) {
                 const bool has = (mlo | mhi) != 0;
-                const int j = mlo ? __builtin_ctz(mlo) : (mhi ? 32 + __builtin_ctz(mhi) : lane);
+                const int j = mlo ? __builtin_ctz(mlo) : (mhi ? 32 + __builtin_ctz(mhi) : 0);
                 if (mlo)
                     mlo &= mlo - 1;
                 else if (mhi)
                     mhi &= mhi - 1;
-                const T px = __shfl(cxp, j), py = __shfl(cyp, j), pz = __shfl(czp, j),
-                        pq = __shfl(cq, j);
-                const T dx = me.x - px, dy = me.y - py, dz = me.z - pz;
-                T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                r2 = has ? r2 : (T)1;
-                const T ri = rsq(r2);
-                T ec, gs;
-                erfc_gauss(a, alpha * (r2 * ri), ec, gs);
-                const T qj = has ? pq : (T)0;
-                const T er = ec * ri;
-                sp = fma(qj, er, sp);
-                const T fm = qj * fma(c2a, gs, er) * (ri * ri);
-                sfx = fma(fm, dx, sfx);
-                sfy = fma(fm, dy, sfy);
-                sfz = fma(fm, dz, sfz);
+                pair_term(a, me, blk[j], has, alpha, c2a, sp, sfx, sfy, sfz);
             }
-            aphi += (double)sp;
-            afx += (double)sfx;
-            afy += (double)sfy;
-            afz += (double)sfz;
+        }
+        aphi += (double)sp;
+        afx += (double)sfx;
+        afy += (double)sfy;
+        afz += (double)sfz;
+        fill = 0;
+    };
+
+    // stage the candidates [b, e) seen through the periodic shift (sx, sy)
+    auto range = [&](int b, int e, T sx, T sy) {
+        for (int c0 = b; c0 < e; c0 += WAVE) {
+            const int nc = min(WAVE, e - c0);
+            if (fill + nc > SR_BUF) flush();
+            if (lane < nc) {
+                Rec4<T> c = srec[c0 + lane];
+                c.x += sx;
+                c.y += sy;
+                buf[fill + lane] = c;
+            }
+            fill += nc;
         }
     };
 
@@ -276,6 +305,7 @@ __global__ __launch_bounds__(SR_WAVES *WAVE) void k_short_tiles(
             xa = run_end + 1;
         }
     }
+    if (fill > 0) flush();
     if (valid) {
         const int o = perm[i];
         if (phi) phi[o] = (T)aphi;
