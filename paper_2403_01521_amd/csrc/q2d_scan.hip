@@ -1003,7 +1003,12 @@ __global__ __launch_bounds__(256) void k_cfold(const CArgs<T> a, int nr, cx<doub
 // of several ranges at once): exclusive scan of the range transfers in the
 // direction of propagation; leaves the carry into each range in the c plane.
 // Each thread composes a run of ceil(nr / TPC) ranges serially, then the runs
-// are combined by a Hillis-Steele scan in LDS and re-walked.
+// are combined by a Hillis-Steele scan in LDS and re-walked.  A run's
+// transfers are loaded CSCAN_PRE at a time, every load in bounds (position
+// and column clamped) and none behind a branch, so that they are in flight
+// together; a run of at most CSCAN_PRE stays in registers for the re-walk.
+constexpr int CSCAN_PRE = 8;
+
 template <int CPG, int TPC>
 __global__ __launch_bounds__(CPG *TPC) void k_cscan(int ncols, int nr, cx<double> *rc) {
     __shared__ cx<double> sc[TPC][CPG], sd[TPC][CPG];
@@ -1015,16 +1020,29 @@ __global__ __launch_bounds__(CPG *TPC) void k_cscan(int ncols, int nr, cx<double
     for (int dir = 0; dir < 2; ++dir) {
         // thread t owns propagation positions [t*per, (t+1)*per)
         auto at = [&](int pos) { return rc_at(ncols, nr, dir, dir ? nr - 1 - pos : pos, col); };
-        cx<double> c{0.0, 0.0}, D{1.0, 0.0};
-        for (int k = 0; k < per; ++k) {
-            const int pos = t * per + k;
-            if (live && pos < nr) {
-                const int64_t o = at(pos);
-                cx<double> cr = rc[o], Dr = rc[plane + o];
-                compose(cr, Dr, c, D);
-                c = cr;
-                D = Dr;
+        auto ok = [&](int k) { return live && k < per && t * per + k < nr; };
+        cx<double> cr[CSCAN_PRE], Dr[CSCAN_PRE];
+        auto load = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < CSCAN_PRE; ++u) {
+                const int pos = min(t * per + k0 + u, nr - 1);
+                const int64_t o =
+                    rc_at(ncols, nr, dir, dir ? nr - 1 - pos : pos, live ? col : ncols - 1);
+                cr[u] = rc[o];
+                Dr[u] = rc[plane + o];
             }
+        };
+        cx<double> c{0.0, 0.0}, D{1.0, 0.0};
+        for (int k0 = 0; k0 < per; k0 += CSCAN_PRE) {
+            load(k0);
+#pragma unroll
+            for (int u = 0; u < CSCAN_PRE; ++u)
+                if (ok(k0 + u)) {
+                    cx<double> nc = cr[u], nD = Dr[u];
+                    compose(nc, nD, c, D);
+                    c = nc;
+                    D = nD;
+                }
         }
         sc[t][cl] = c;
         sd[t][cl] = D;
@@ -1044,16 +1062,16 @@ __global__ __launch_bounds__(CPG *TPC) void k_cscan(int ncols, int nr, cx<double
         }
         cx<double> cin = t > 0 ? sc[t - 1][cl] : cx<double>{0.0, 0.0};
         __syncthreads();
-        for (int k = 0; k < per; ++k) {
-            const int pos = t * per + k;
-            if (live && pos < nr) {
-                const int64_t o = at(pos);
-                const cx<double> cr = rc[o], Dr = rc[plane + o];
-                rc[o] = cin;
-                cx<double> nc = cr, nD = Dr;
-                compose(nc, nD, cin, cx<double>{0.0, 0.0});
-                cin = nc;
-            }
+        for (int k0 = 0; k0 < per; k0 += CSCAN_PRE) {
+            if (per > CSCAN_PRE) load(k0);
+#pragma unroll
+            for (int u = 0; u < CSCAN_PRE; ++u)
+                if (ok(k0 + u)) {
+                    rc[at(t * per + k0 + u)] = cin;
+                    cx<double> nc = cr[u], nD = Dr[u];
+                    compose(nc, nD, cin, cx<double>{0.0, 0.0});
+                    cin = nc;
+                }
         }
         __syncthreads();
     }
