@@ -31,6 +31,15 @@ __host__ __device__ inline cx<T> cadd(cx<T> a, cx<T> b) {
     return {a.re + b.re, a.im + b.im};
 }
 
+// e^{-beta t} for the spans tables of the segmented carry scans (FP64: the
+// carries are built from them); one definition for the k != 0 and k = 0 passes
+__device__ inline cx<double> span_decay(double br, double bi, double t) {
+    double sn, cs;
+    sincos(bi * t, &sn, &cs);
+    const double m = exp(-br * t);
+    return {m * cs, -m * sn};
+}
+
 // SOE pair representatives passed to kernels by value.
 struct PairParams {
     int mh;                       // number of conjugate pairs used

@@ -26,7 +26,6 @@
 namespace q2d {
 
 q2d_status carry_k0(Plan *p, int nseg, int S, int64_t N);
-q2d_status spans_k0(Plan *p, int nseg, int S, int64_t N);
 
 namespace {
 
@@ -77,6 +76,15 @@ struct K0Lds {
     double cf[10][MAX_PAIRS];
 };
 
+// the aggregate kernel's LDS: heights, sources and the pair exponents only
+// (a third of the sweep's, so that it runs at its register-limited occupancy)
+template <typename T, int LG>
+struct K0AggLds {
+    static constexpr int G = WAVE / LG;
+    T z[G][ZP], q[G][ZP];
+    double br[MAX_PAIRS], bi[MAX_PAIRS];
+};
+
 // the pair tables, copied with uniform indices (a lane-dependent index into
 // the kernel-argument struct would compile to select chains over all entries)
 template <typename T, int LG>
@@ -98,10 +106,9 @@ __device__ inline void k0_coefs(const PairParams &pp, K0Lds<T, LG> &L) {
 }
 
 // heights and sources of the wave's segments (zero past N)
-template <typename T, int LG>
+template <typename T, int G, typename LDS>
 __device__ inline void k0_stage(const T *__restrict__ zs, const T *__restrict__ qs, int64_t N,
-                                int seg0, K0Lds<T, LG> &L) {
-    constexpr int G = K0Lds<T, LG>::G;
+                                int seg0, LDS &L) {
     for (int e = threadIdx.x; e < G * S0; e += WAVE) {
         const int g = e / S0, j = e % S0;
         const int64_t i = (int64_t)(seg0 + g) * S0 + j;
@@ -127,23 +134,36 @@ __device__ inline double group_sum(const double (&v)[LG], double (*rb)[LG + 1], 
     return s;
 }
 
+// Segment aggregates, and the spans of the k = 0 carry scan: W = e^{-beta
+// (z_last - z_first)}, G = e^{-beta (z_first(next) - z_last)} per (segment,
+// pair), the same values the k != 0 spans kernel forms for its segments.
 template <typename T, int LG>
 __global__ __launch_bounds__(WAVE) void k0_agg(const T *__restrict__ zs, const T *__restrict__ qs,
                                                int64_t N, int nseg, PairParams pp,
-                                               cx<double> *__restrict__ agg) {
-    constexpr int G = K0Lds<T, LG>::G;
-    __shared__ K0Lds<T, LG> L;
+                                               cx<double> *__restrict__ agg,
+                                               cx<double> *__restrict__ spans) {
+    constexpr int G = K0AggLds<T, LG>::G;
+    __shared__ K0AggLds<T, LG> L;
     const int g = threadIdx.x / LG, l = threadIdx.x % LG;
     const int seg0 = blockIdx.x * G, seg = seg0 + g;
-    k0_coefs<T, LG>(pp, L);
-    k0_stage<T, LG>(zs, qs, N, seg0, L);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < pp.mh; ++k) {
+            L.br[k] = pp.beta_re[k];
+            L.bi[k] = pp.beta_im[k];
+        }
+    }
+    k0_stage<T, G>(zs, qs, N, seg0, L);
     if (seg >= nseg) return;
     const int n = (int)min((int64_t)S0, N - (int64_t)seg * S0);
     const int ns = pp.mh + 1;
     const T *z = L.z[g], *q = L.q[g];
     if (l < pp.mh) {
+        const double br = L.br[l], bi = L.bi[l];
+        const double zf = (double)z[0], zl = (double)z[n - 1];
+        const double zn = seg + 1 < nseg ? (double)zs[(int64_t)(seg + 1) * S0] : zl;
+        spans[((int64_t)seg * pp.mh + l) * 2] = span_decay(br, bi, zl - zf);
+        spans[((int64_t)seg * pp.mh + l) * 2 + 1] = span_decay(br, bi, zn - zl);
         // forward: referenced to the segment's last particle; backward: to its first
-        const double br = L.cf[0][l], bi = L.cf[1][l];
         cx<double> fq{0, 0}, fz{0, 0}, bq{0, 0}, bz{0, 0}, e{1, 0};
         for (int j = 0; j < n; ++j) {
             const cx<double> d = j ? cexpm64(br, bi, z[j] - z[j - 1]) : cx<double>{1, 0};
@@ -192,7 +212,7 @@ __global__ __launch_bounds__(WAVE) void k0_sweep(const T *__restrict__ zs,
     const int g = threadIdx.x / LG, l = threadIdx.x % LG;
     const int seg0 = blockIdx.x * G, seg = seg0 + g;
     k0_coefs<T, LG>(pp, L);
-    k0_stage<T, LG>(zs, qs, N, seg0, L);
+    k0_stage<T, G>(zs, qs, N, seg0, L);
     const int n = seg < nseg ? (int)min((int64_t)S0, N - (int64_t)seg * S0) : 0;
     const int ns = pp.mh + 1;
     const bool act = n > 0 && l < pp.mh;
@@ -296,12 +316,13 @@ static q2d_status k0_launch(Plan *p, int64_t N, int nseg, const void *qsrc, doub
                             const double *rep_tpa, const int32_t *seg_rep, int seg_div) {
     const int nb = (nseg + K0Lds<float, LG>::G - 1) / K0Lds<float, LG>::G;
     cx<double> *agg = (cx<double> *)p->agg0.p;
+    cx<double> *spans = (cx<double> *)p->spans0.p;
     if (p->fp32)
-        k0_agg<float, LG><<<nb, WAVE, 0, p->stream>>>((const float *)p->s_z.p,
-                                                       (const float *)qsrc, N, nseg, p->pp, agg);
+        k0_agg<float, LG><<<nb, WAVE, 0, p->stream>>>(
+            (const float *)p->s_z.p, (const float *)qsrc, N, nseg, p->pp, agg, spans);
     else
-        k0_agg<double, LG><<<nb, WAVE, 0, p->stream>>>((const double *)p->s_z.p,
-                                                        (const double *)qsrc, N, nseg, p->pp, agg);
+        k0_agg<double, LG><<<nb, WAVE, 0, p->stream>>>(
+            (const double *)p->s_z.p, (const double *)qsrc, N, nseg, p->pp, agg, spans);
     q2d_status st = carry_k0(p, nseg, S0, N);
     if (st != Q2D_OK) return st;
     if (p->fp32)
@@ -335,7 +356,6 @@ q2d_status k0_run(Plan *p, int64_t N) {
     Reqs req;
     k0_reqs(p, N, req);
     if ((st = ensure_all(p, req)) != Q2D_OK) return st;
-    if ((st = spans_k0(p, nseg, S0, N)) != Q2D_OK) return st;
     const void *qsrc = p->src ? p->src : p->s_q.p;
     const double PI = 3.14159265358979323846;
     const double tpa = 2.0 * PI / (p->Lx * p->Ly);

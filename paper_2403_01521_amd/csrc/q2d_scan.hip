@@ -103,13 +103,6 @@ __device__ inline cx<double> cexpm(double br, double bi, double t) {
     sincos(ai, &s, &c);
     return {m * c, -m * s};
 }
-// e^{-beta t} for the spans tables (FP64: the carries are built from them)
-__device__ inline cx<double> span_decay(double br, double bi, double t) {
-    double sn, cs;
-    sincos(bi * t, &sn, &cs);
-    const double m = exp(-br * t);
-    return {m * cs, -m * sn};
-}
 __device__ inline float expm_real(float k, float t) { return __expf(-k * t); }
 __device__ inline double expm_real(double k, double t) { return exp(-k * t); }
 // e^{-k t} from a coefficient scaled once: FP32 keeps kl = -k log2(e) and
@@ -1448,19 +1441,6 @@ q2d_status carry_k0(Plan *p, int nseg, int S, int64_t N) {
         ca.seg_div = p->S_batch / S;
     }
     return carry_run<double, false>(p, ca, p->carry_tmp0);
-}
-
-// spans for the k = 0 segmentation (z in the plan's precision)
-q2d_status spans_k0(Plan *p, int nseg, int S, int64_t N) {
-    const int64_t n = (int64_t)nseg * p->mh;
-    if (n == 0) return Q2D_OK;
-    if (p->fp32)
-        k_spans<float><<<(int)((n + 255) / 256), 256, 0, p->stream>>>(
-            (const float *)p->s_z.p, N, S, nseg, p->pp, (cx<double> *)p->spans0.p);
-    else
-        k_spans<double><<<(int)((n + 255) / 256), 256, 0, p->stream>>>(
-            (const double *)p->s_z.p, N, S, nseg, p->pp, (cx<double> *)p->spans0.p);
-    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
 }
 
 }  // namespace q2d
