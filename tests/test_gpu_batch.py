@@ -223,6 +223,39 @@ def test_batch_graph_replay_matches_eager(soe_tables):
     graph.close()
 
 
+def test_batch_graph_dropped_when_scratch_grows(soe_tables):
+    """A graph holds the addresses of the scratch it was captured with.  An
+    eager step with a larger P grows the mode tables and aggregates; replay
+    must then refuse (Q2D_EUNSUPPORTED) or, if nothing moved, replay exactly
+    the captured step.  A new capture afterwards works again."""
+    pos, q, boxes, counts = small_batch(np.float32)
+    w, s = soe_tables[16]
+    seed, step0 = 31, 2
+    b = q2d.Batch(boxes, counts, ALPHA, w, s, precision="fp32", p_max=P)
+    ref_b = q2d.Batch(boxes, counts, ALPHA, w, s, precision="fp32", p_max=P)
+    gp, gq = dev(pos, torch.float32), dev(q, torch.float32)
+    phi_g, F_g, E_g = b.capture(gp, gq, 32, seed, step0)
+    b.rbm_step(gp, gq, P, seed, step0 + 100)
+    torch.cuda.synchronize()
+    try:
+        b.replay(1)
+    except q2d.Q2DError as e:
+        assert e.code == q2d.Q2D_EUNSUPPORTED, e
+    else:
+        torch.cuda.synchronize()
+        ref = ref_b.rbm_step(gp, gq, 32, seed, step0)
+        torch.cuda.synchronize()
+        assert torch.equal(phi_g, ref[0]) and torch.equal(F_g, ref[1])
+    phi_g, F_g, E_g = b.capture(gp, gq, P, seed, step0)
+    b.replay(1)
+    torch.cuda.synchronize()
+    ref = ref_b.rbm_step(gp, gq, P, seed, step0)
+    torch.cuda.synchronize()
+    assert torch.equal(phi_g, ref[0]) and torch.equal(F_g, ref[1]) and torch.equal(E_g, ref[2])
+    b.close()
+    ref_b.close()
+
+
 def test_batch_tune(soe_tables):
     pos, q, boxes, counts = small_batch(np.float32)
     w, s = soe_tables[16]

@@ -10,7 +10,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-from _parity import assert_close  # noqa: E402
+from _parity import assert_close, assert_energy  # noqa: E402
 
 torch = pytest.importorskip("torch")
 
@@ -167,6 +167,42 @@ def test_ragged_sizes_fp64(soe_tables, n):
     print("ragged", n, rel(phi, r["phi"]), rel(F, r["F"]))
     assert_close(phi, r["phi"], 1e-10)
     assert_close(F, r["F"], 1e-10)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_clustered_heights(soe_tables, prec, tol):
+    """Heights packed into a layer 0.004 thick (6000 particles) and 1500 at one
+    height (ties), 500 more spread over the box: sort keys that share most of
+    their bits and long runs of equal keys.  Random batch step against the
+    oracle on the same modes."""
+    dtn = np.float32 if prec == "fp32" else np.float64
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    rng = np.random.default_rng(4242)
+    box, alpha, P = (40.0, 40.0, 10.0), 0.25, 32
+    n_thin, n_tie, n_rest = 6000, 1500, 500
+    n = n_thin + n_tie + n_rest
+    z = np.concatenate([rng.uniform(2.0, 2.004, n_thin), np.full(n_tie, 7.5),
+                        rng.uniform(0.0, 10.0, n_rest)])
+    pos = np.stack([rng.uniform(0, box[0], n), rng.uniform(0, box[1], n), z], axis=1)
+    q = rng.permutation(np.repeat([1.0, -1.0], n // 2))
+    pos, q = pos.astype(dtn), q.astype(dtn)
+    w, s = soe_tables[16]
+    plan = q2d.Plan(box, alpha, w, s, precision=prec, n_max=n, p_max=P)
+    phi, F, E, modes = plan.rbm_step(dev(pos, dt), dev(q, dt), P, seed=5, step=2)
+    torch.cuda.synchronize()
+    phi = phi.cpu().numpy().astype(np.float64)
+    F = F.cpu().numpy().astype(np.float64)
+    E = float(E.cpu()[0])
+    modes = modes.cpu().numpy()
+    H = lattice.H_direct(box[0], box[1], alpha)
+    D = soewald2d.diag_constant(box[0], box[1], alpha, w, s)
+    r = o3.long_range(pos, q, box, alpha, w, s, modes, soewald2d.rb_weights(P, H, box[0], box[1]),
+                      include_self_pair=False, diag=D, nthreads=8)
+    print("clustered", prec, rel(phi, r["phi"]), rel(F, r["F"]), abs(E - r["U"]) / abs(r["U"]))
+    assert_close(phi, r["phi"], tol)
+    assert_close(F, r["F"], tol)
+    assert_energy(E, r["U"], q, r["phi"], tol)
+    plan.close()
 
 
 def test_equal_heights_square_lattice(soe_tables):
