@@ -3,12 +3,21 @@
 // The recursion of Sec. 3.2 needs the particles ordered by height z (i > j
 // <=> z_i >= z_j) so that every exponent in the scans is non-positive (the
 // stability remark after eq. 35).  Sort keys are the IEEE bit patterns of z:
-// for z >= 0 they order like the numbers (z + 0 turns -0 into +0).  The sort
-// is a least-significant-digit radix sort with 8-bit digits; each pass is
-// stable, so equal heights keep input order.
+// for z >= 0 they order like the numbers (z + 0 turns -0 into +0).  The order
+// is that of the pairs (key, input index): equal heights keep input order.
 //
-// One pass = (1) per-tile digit histograms, (2) per-digit exclusive scan over
-// tiles, (3) a stable scatter that ranks keys inside a tile with wave ballots.
+// The radix sort: least-significant digit first, 8-bit digits, each pass
+// stable.  One pass = (1) per-tile digit histograms, (2) per-digit exclusive
+// scan over tiles, (3) a stable scatter that ranks keys inside a tile with
+// wave ballots.
+//
+// Single systems up to ~1.2e6 particles (FP32; ~6e5 FP64) take a bucket sort
+// built from the same parts: one stable scatter whose digit is the z bucket
+// floor(256 z / L_z) (monotone in z), then one work-group per bucket runs the
+// radix sort in LDS on the bucket's keys minus its smallest key, with only as
+// many passes as that span needs.  The bucket arrives in input order, so the
+// result is the (key, index) order.  A bucket too large for LDS (strongly
+// clustered heights) is sorted in global memory by a bitonic network.
 #include "q2d_internal.h"
 
 namespace q2d {
@@ -27,6 +36,18 @@ __device__ inline uint64_t zkey(double z) {
 // Status bits in the device status word (bit q2d_status).
 __device__ inline void set_status(int *st, int code) { atomicOr(st, 1 << code); }
 
+// z buckets of the bucket sort: floor(z * scale) clamped to [0, nb - 1], with
+// scale = nb / L_z rounded once in the keys' precision; monotone in z (a
+// product by a positive constant and the floor both keep order)
+constexpr int BK_NB = 256;  // buckets: one digit of the scatter below
+template <typename T>
+__device__ inline uint32_t zbucket(T z, T scale, uint32_t nb) {
+    const T v = z * scale;
+    return v >= (T)nb ? nb - 1 : (v > (T)0 ? (uint32_t)v : 0u);
+}
+__device__ inline float key_z(uint32_t k) { return __uint_as_float(k); }
+__device__ inline double key_z(uint64_t k) { return __longlong_as_double((long long)k); }
+
 // one particle's position and charge in one aligned record: the gather after
 // the sort then reads one record per particle instead of two scattered ones
 template <typename T>
@@ -36,13 +57,13 @@ struct alignas(4 * sizeof(T)) Rec {
 
 // One sort tile per work-group (SORT_ITEMS particles per thread, coalesced):
 // keys, identity values and records in input order, plus the tile's
-// histogram of the first digit, so the first sort pass needs no histogram
-// launch of its own.
-template <typename T, typename K>
+// histogram of the first digit, the z bucket (BUCKET) or the key's low byte,
+// so the first scatter needs no histogram launch of its own.
+template <typename T, typename K, bool BUCKET>
 __global__ __launch_bounds__(SORT_THREADS) void k_stage(
     const T *__restrict__ pos, const T *__restrict__ q, int64_t N, K *__restrict__ keys,
     int32_t *__restrict__ vals, Rec<T> *__restrict__ rec, uint32_t *__restrict__ hist, int ntiles,
-    double Lz, int validate, int *status, double *qsums) {
+    T scale, double Lz, int validate, int *status, double *qsums) {
     __shared__ uint32_t h[256];
     const int t = threadIdx.x;
     h[t] = 0;
@@ -58,7 +79,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_stage(
             keys[i] = key;
             vals[i] = (int32_t)i;
             rec[i] = Rec<T>{pos[3 * i], pos[3 * i + 1], z, q[i]};
-            atomicAdd(&h[(uint32_t)key & 255u], 1u);
+            atomicAdd(&h[BUCKET ? zbucket(key_z(key), scale, (uint32_t)BK_NB)
+                                : (uint32_t)key & 255u],
+                      1u);
             if (validate) {
                 const T x = pos[3 * i], y = pos[3 * i + 1];
                 const double qv = (double)q[i];
@@ -149,11 +172,21 @@ __global__ __launch_bounds__(256) void k_scan_digit(uint32_t *__restrict__ hist,
     if (t == 255) tot[d] = part[255];
 }
 
-template <typename K>
+// digit of a key: its byte at shift, or its z bucket (BUCKET; scale as in k_stage)
+template <typename K, bool BUCKET>
+__device__ inline uint32_t key_digit(K k, int shift, double scale) {
+    if (BUCKET) {
+        using Z = decltype(key_z(k));
+        return zbucket(key_z(k), (Z)scale, (uint32_t)BK_NB);
+    }
+    return (uint32_t)(k >> shift) & 255u;
+}
+
+template <typename K, bool BUCKET = false>
 __global__ __launch_bounds__(SORT_THREADS) void k_scatter(
     const K *__restrict__ kin, const int32_t *__restrict__ vin, K *__restrict__ kout,
     int32_t *__restrict__ vout, int64_t N, int shift, const uint32_t *__restrict__ hist,
-    const uint32_t *__restrict__ tot, int ntiles) {
+    const uint32_t *__restrict__ tot, int ntiles, double scale = 0.0) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t run[256];
     __shared__ uint32_t wc[SORT_THREADS / WAVE][256];
@@ -192,7 +225,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(
         const bool valid = i < N;
         const K k = ks[r];
         const int32_t v = vs[r];
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t d = key_digit<K, BUCKET>(k, shift, scale);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -218,6 +251,221 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(
         }
         run[t] += add;
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-bucket sort of the bucket sort (one work-group per bucket)
+// ---------------------------------------------------------------------------
+constexpr int BK_THREADS = 1024;
+constexpr int BK_WAVES = BK_THREADS / WAVE;
+// largest bucket sorted in LDS (two key and two index buffers): 144 KB of LDS
+// with 32-bit keys, 112 KB with 64-bit keys
+template <typename K>
+constexpr int bk_cap() {
+    return sizeof(K) == 4 ? 8192 : 4096;
+}
+
+// (key, index) order: a total order, so a sorted bucket is unique
+template <typename K>
+__device__ inline bool bk_less(K ka, int32_t ia, K kb, int32_t ib) {
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+// Bitonic network with every comparator ascending (the first half-cleaner of a
+// merge of size 2^lk pairs offsets o and 2^lk - 1 - o): it sorts any length n
+// by treating the positions n .. m - 1 (m = next power of two) as +infinity,
+// which never move, so comparators that reach past n are skipped.  Comparator
+// c of the stage (merge 2^lk, distance 2^lj) joins positions i < p.  Used in
+// global memory for buckets too large for LDS.
+__device__ inline void bk_pair(int c, int lk, int lj, int &i, int &p) {
+    const int j = 1 << lj;
+    if (lj == lk - 1) {
+        const int blk = c >> lj, o = c & (j - 1);
+        i = (blk << lk) + o;
+        p = (blk << lk) + (1 << lk) - 1 - o;
+    } else {
+        i = ((c >> lj) << (lj + 1)) + (c & (j - 1));
+        p = i + j;
+    }
+}
+
+template <typename K>
+__device__ inline void bk_bitonic(K *key, int32_t *idx, int n) {
+    int lm = 0;
+    while ((1 << lm) < n) ++lm;
+    const int half = (1 << lm) >> 1;
+    for (int lk = 1; lk <= lm; ++lk)
+        for (int lj = lk - 1; lj >= 0; --lj) {
+            for (int c = threadIdx.x; c < half; c += BK_THREADS) {
+                int i, p;
+                bk_pair(c, lk, lj, i, p);
+                if (p < n) {
+                    const K ki = key[i], kp = key[p];
+                    const int32_t ii = idx[i], ip = idx[p];
+                    if (bk_less<K>(kp, ip, ki, ii)) {
+                        key[i] = kp;
+                        key[p] = ki;
+                        idx[i] = ip;
+                        idx[p] = ii;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+}
+
+// LDS of the per-bucket radix sort
+template <typename K>
+struct BkLds {
+    static constexpr int CAP = bk_cap<K>();
+    K ka[CAP], kb[CAP];
+    int32_t ia[CAP], ib[CAP];
+    uint32_t hw[BK_WAVES][256];   // per-wave digit counts of a pass
+    uint16_t pos[BK_WAVES][256];  // next output position of (wave, digit)
+    uint32_t wtot[4];
+    K kred[2][BK_WAVES];
+    uint32_t below[BK_WAVES];
+};
+
+// One stable LSD pass in LDS on the digit ((key - kmin) >> shift) & 255.  Wave
+// w owns the contiguous slice [w0, w1) of the (index-ordered) elements: the
+// per-wave counts and one prefix over (digit, wave) give every wave its
+// output positions, then each wave ranks its slice in rounds of 64 with
+// ballots and advances its own positions (no work-group barrier per round).
+template <typename K>
+__device__ inline void bk_radix_pass(const K *ks, const int32_t *is, K *kd, int32_t *id, int n,
+                                     K kmin, int shift, BkLds<K> &L) {
+    const int t = threadIdx.x, lane = t % WAVE, wave = t / WAVE;
+    const int per = (n + BK_WAVES - 1) / BK_WAVES;
+    const int w0 = min(wave * per, n), w1 = min(w0 + per, n);
+    auto digit = [&](K k) { return (uint32_t)((k - kmin) >> shift) & 255u; };
+    for (int d = lane; d < 256; d += WAVE) L.hw[wave][d] = 0u;
+    for (int x = w0 + lane; x < w1; x += WAVE) atomicAdd(&L.hw[wave][digit(ks[x])], 1u);
+    __syncthreads();
+    // digit totals, their exclusive scan (4 waves of 64 digits), then the
+    // (digit, wave) positions
+    uint32_t td = 0, v = 0;
+    if (t < 256) {
+#pragma unroll
+        for (int w = 0; w < BK_WAVES; ++w) td += L.hw[w][t];
+        v = td;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const uint32_t u = __shfl_up(v, off);
+            if (lane >= off) v += u;
+        }
+        if (lane == WAVE - 1) L.wtot[wave] = v;
+    }
+    __syncthreads();
+    if (t < 256) {
+        uint32_t off = v - td;
+        for (int w = 0; w < wave; ++w) off += L.wtot[w];
+#pragma unroll
+        for (int w = 0; w < BK_WAVES; ++w) {
+            L.pos[w][t] = (uint16_t)off;
+            off += L.hw[w][t];
+        }
+    }
+    __syncthreads();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int r0 = w0; r0 < w1; r0 += WAVE) {
+        const int x = r0 + lane;
+        const bool valid = x < w1;
+        const K k = valid ? ks[x] : kmin;
+        const int32_t ix = valid ? is[x] : 0;
+        const uint32_t d = digit(k);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb) {
+            const bool bit = (d >> bb) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        // every lane reads its digit's position before the group's first lane
+        // advances it (one wave: its LDS operations complete in order)
+        const uint32_t at = (uint32_t)L.pos[wave][d] + rank;
+        if (valid) {
+            kd[at] = k;
+            id[at] = ix;
+        }
+        if (valid && rank == 0) L.pos[wave][d] = (uint16_t)(at + (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+}
+
+// One work-group per bucket: sort it by (key, index).  The bucket is the scan's
+// digit total tot[b] long and starts at the sum of the totals below it; it
+// holds its particles in input order (the bucket scatter is stable), so a
+// stable radix sort on the keys leaves it in (key, index) order.  Only the
+// bits that vary inside the bucket are sorted (keys minus the smallest).
+template <typename K>
+__global__ __launch_bounds__(BK_THREADS) void k_bsort(K *__restrict__ keys,
+                                                     int32_t *__restrict__ vals,
+                                                     const uint32_t *__restrict__ tot) {
+    __shared__ BkLds<K> L;
+    const int b = blockIdx.x, t = threadIdx.x, lane = t % WAVE, wave = t / WAVE;
+    const int n = (int)tot[b];
+    if (n <= 1) return;
+    // start = sum of tot[0 .. b - 1] (fixed order: wave sums, then the waves)
+    uint32_t v = t < b ? tot[t] : 0u;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) L.below[wave] = v;
+    __syncthreads();
+    int64_t base = 0;
+#pragma unroll
+    for (int w = 0; w < BK_WAVES; ++w) base += L.below[w];
+    if (n > BkLds<K>::CAP) {
+        // strongly clustered heights: in place in the work-group's own
+        // global-memory region (visible to its threads across the barriers)
+        bk_bitonic<K>(keys + base, vals + base, n);
+        return;
+    }
+    K lo = ~(K)0, hi = (K)0;
+    for (int x = t; x < n; x += BK_THREADS) {
+        const K k = keys[base + x];
+        L.ka[x] = k;
+        L.ia[x] = vals[base + x];
+        lo = min(lo, k);
+        hi = max(hi, k);
+    }
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        lo = min(lo, (K)__shfl_xor(lo, off));
+        hi = max(hi, (K)__shfl_xor(hi, off));
+    }
+    if (lane == 0) {
+        L.kred[0][wave] = lo;
+        L.kred[1][wave] = hi;
+    }
+    __syncthreads();
+    K kmin = L.kred[0][0], kmax = L.kred[1][0];
+#pragma unroll
+    for (int w = 1; w < BK_WAVES; ++w) {
+        kmin = min(kmin, L.kred[0][w]);
+        kmax = max(kmax, L.kred[1][w]);
+    }
+    const K span = kmax - kmin;
+    if (span == 0) return;  // one key: the bucket is in input order already
+    const int bits = (int)(8 * sizeof(K)) -
+                     (sizeof(K) == 4 ? __clz((uint32_t)span) : __clzll((unsigned long long)span));
+    const int passes = (bits + 7) / 8;
+    K *sk = L.ka, *dk = L.kb;
+    int32_t *si = L.ia, *di = L.ib;
+    for (int p = 0; p < passes; ++p) {
+        bk_radix_pass<K>(sk, si, dk, di, n, kmin, 8 * p, L);
+        K *tk = sk;
+        sk = dk;
+        dk = tk;
+        int32_t *ti = si;
+        si = di;
+        di = ti;
+    }
+    for (int x = t; x < n; x += BK_THREADS) {
+        keys[base + x] = sk[x];
+        vals[base + x] = si[x];
     }
 }
 
@@ -288,6 +536,13 @@ q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
     sort_reqs_t<T, K>(p, N, req);
     if ((st = ensure_all(p, req)) != Q2D_OK) return st;
     const int ntiles = (int)((N + SORT_TILE - 1) / SORT_TILE);
+    // the bucket sort while the average bucket stays well inside the LDS sort
+    // (denser layers and fluctuations then fit as well); Q2D_RADIX_SORT=1
+    // takes the radix sort at any size (both give the same order)
+    const bool bucket = N <= (int64_t)BK_NB * bk_cap<K>() * 6 / 10 &&
+                        env_int("Q2D_RADIX_SORT", 0) == 0;
+    // bucket scale BK_NB / L_z, rounded once in the keys' precision
+    const double scale = (double)BK_NB / p->Lz;
 
     int *status = (int *)p->status.p;
     double *qsums = (double *)((char *)p->status.p + 16);
@@ -295,25 +550,39 @@ q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
     if (p->opts.validate) k_zero2<<<1, 1, 0, p->stream>>>(qsums);
     uint32_t *hist = (uint32_t *)p->hist.p;
     uint32_t *tot = hist + (size_t)256 * ntiles;
-    k_stage<T, K><<<ntiles, SORT_THREADS, 0, p->stream>>>(
-        pos, q, N, (K *)p->keys_a.p, (int32_t *)p->vals_a.p, (Rec<T> *)p->recs.p, hist, ntiles,
-        p->Lz, p->opts.validate, status, qsums);
-    if (p->opts.validate) k_neutral_check<<<1, 1, 0, p->stream>>>(qsums, status);
-
     K *kin = (K *)p->keys_a.p, *kout = (K *)p->keys_b.p;
     int32_t *vin = (int32_t *)p->vals_a.p, *vout = (int32_t *)p->vals_b.p;
-    const int passes = (int)sizeof(K);
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = 8 * pass;
-        // (k_stage wrote the first pass's tile histograms)
-        if (pass > 0) k_hist<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, N, shift, hist, ntiles);
+    if (bucket)
+        k_stage<T, K, true><<<ntiles, SORT_THREADS, 0, p->stream>>>(
+            pos, q, N, kin, vin, (Rec<T> *)p->recs.p, hist, ntiles, (T)scale, p->Lz,
+            p->opts.validate, status, qsums);
+    else
+        k_stage<T, K, false><<<ntiles, SORT_THREADS, 0, p->stream>>>(
+            pos, q, N, kin, vin, (Rec<T> *)p->recs.p, hist, ntiles, (T)scale, p->Lz,
+            p->opts.validate, status, qsums);
+    if (p->opts.validate) k_neutral_check<<<1, 1, 0, p->stream>>>(qsums, status);
+    if (bucket) {
+        // one stable scatter by bucket, then every bucket sorted by (key, index)
         k_scan_digit<<<256, 256, 0, p->stream>>>(hist, ntiles, tot);
-        k_scatter<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, vin, kout, vout, N, shift, hist,
-                                                            tot, ntiles);
-        std::swap(kin, kout);
-        std::swap(vin, vout);
+        k_scatter<K, true><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, vin, kout, vout, N, 0,
+                                                                  hist, tot, ntiles, scale);
+        k_bsort<K><<<BK_NB, BK_THREADS, 0, p->stream>>>(kout, vout, tot);
+        p->perm = vout;
+    } else {
+        const int passes = (int)sizeof(K);
+        for (int pass = 0; pass < passes; ++pass) {
+            const int shift = 8 * pass;
+            // (k_stage wrote the first pass's tile histograms)
+            if (pass > 0)
+                k_hist<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, N, shift, hist, ntiles);
+            k_scan_digit<<<256, 256, 0, p->stream>>>(hist, ntiles, tot);
+            k_scatter<K><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, vin, kout, vout, N, shift,
+                                                                hist, tot, ntiles);
+            std::swap(kin, kout);
+            std::swap(vin, vout);
+        }
+        p->perm = vin;
     }
-    p->perm = vin;
     k_gather<T><<<nb, 256, 0, p->stream>>>((const Rec<T> *)p->recs.p, p->perm, N, p->Lx, p->Ly,
                                            (U *)p->s_ux.p, (U *)p->s_uy.p, (T *)p->s_z.p,
                                            (T *)p->s_q.p);

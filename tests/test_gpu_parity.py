@@ -171,15 +171,15 @@ def test_ragged_sizes_fp64(soe_tables, n):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_clustered_heights(soe_tables, prec, tol):
-    """Heights packed into a layer 0.004 thick (6000 particles) and 1500 at one
-    height (ties), 500 more spread over the box: sort keys that share most of
-    their bits and long runs of equal keys.  Random batch step against the
-    oracle on the same modes."""
+    """Heights packed into a layer 0.004 thick (9000 particles: one z bucket
+    of the sort larger than its LDS capacity, sorted in global memory) and
+    1500 at one height (ties: a bucket of equal keys), 500 more spread over
+    the box.  Random batch step against the oracle on the same modes."""
     dtn = np.float32 if prec == "fp32" else np.float64
     dt = torch.float32 if prec == "fp32" else torch.float64
     rng = np.random.default_rng(4242)
     box, alpha, P = (40.0, 40.0, 10.0), 0.25, 32
-    n_thin, n_tie, n_rest = 6000, 1500, 500
+    n_thin, n_tie, n_rest = 9000, 1500, 500
     n = n_thin + n_tie + n_rest
     z = np.concatenate([rng.uniform(2.0, 2.004, n_thin), np.full(n_tie, 7.5),
                         rng.uniform(0.0, 10.0, n_rest)])
@@ -202,6 +202,30 @@ def test_clustered_heights(soe_tables, prec, tol):
     assert_close(phi, r["phi"], tol)
     assert_close(F, r["F"], tol)
     assert_energy(E, r["U"], q, r["phi"], tol)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_sort_paths_agree(soe_tables, prec, monkeypatch):
+    """The bucket sort (systems up to ~1.2e6 particles in FP32) and the radix
+    sort (larger systems; Q2D_RADIX_SORT=1 forces it) realise the same
+    (height, input index) order, so every output is bitwise the same; with
+    ties and a dense layer on the bench workload's height profile."""
+    dtn = np.float32 if prec == "fp32" else np.float64
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    c = wl.make_config(3, dtype=dtn, n_override=200000)
+    pos = c["pos"].copy()
+    pos[:3000, 2] = 4.25
+    pos[3000:9000, 2] = np.linspace(6.0, 6.001, 6000, dtype=dtn)
+    w, s = soe_tables[16]
+    plan = q2d.Plan(c["box"], c["alpha"], w, s, precision=prec, n_max=len(c["q"]), p_max=64)
+    gp, gq = dev(pos, dt), dev(c["q"], dt)
+    a = [t.clone() for t in plan.rbm_step(gp, gq, 64, seed=3, step=1)]
+    monkeypatch.setenv("Q2D_RADIX_SORT", "1")
+    b = [t.clone() for t in plan.rbm_step(gp, gq, 64, seed=3, step=1)]
+    monkeypatch.delenv("Q2D_RADIX_SORT")
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
     plan.close()
 
 
