@@ -15,9 +15,10 @@
 // built from the same parts: one stable scatter whose digit is the z bucket
 // floor(256 z / L_z) (monotone in z), then one work-group per bucket runs the
 // radix sort in LDS on the bucket's keys minus its smallest key, with only as
-// many passes as that span needs.  The bucket arrives in input order, so the
-// result is the (key, index) order.  A bucket too large for LDS (strongly
-// clustered heights) is sorted in global memory by a bitonic network.
+// many passes as that span needs, and stages its part of the sorted arrays.
+// The bucket arrives in input order, so the result is the (key, index)
+// order.  A bucket too large for LDS (strongly clustered heights) is sorted in
+// global memory by a bitonic network.
 #include "q2d_internal.h"
 
 namespace q2d {
@@ -254,6 +255,23 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(
     }
 }
 
+template <typename T>
+struct Fix;
+template <>
+struct Fix<float> {
+    using U = uint32_t;
+    __device__ static U frac(double v) {
+        // fixed-point fraction of a turn: round(frac(v) * 2^32) mod 2^32
+        double f = v - floor(v);
+        return (U)(uint64_t)llrint(f * 4294967296.0);
+    }
+};
+template <>
+struct Fix<double> {
+    using U = double;
+    __device__ static U frac(double v) { return v - floor(v); }
+};
+
 // ---------------------------------------------------------------------------
 // per-bucket sort of the bucket sort (one work-group per bucket)
 // ---------------------------------------------------------------------------
@@ -399,15 +417,21 @@ __device__ inline void bk_radix_pass(const K *ks, const int32_t *is, K *kd, int3
 // digit total tot[b] long and starts at the sum of the totals below it; it
 // holds its particles in input order (the bucket scatter is stable), so a
 // stable radix sort on the keys leaves it in (key, index) order.  Only the
-// bits that vary inside the bucket are sorted (keys minus the smallest).
-template <typename K>
+// bits that vary inside the bucket are sorted (keys minus the smallest).  The
+// work-group then stages its bucket's part of the sorted arrays (the gather:
+// one record per particle through the permutation).
+template <typename T, typename K>
 __global__ __launch_bounds__(BK_THREADS) void k_bsort(K *__restrict__ keys,
                                                      int32_t *__restrict__ vals,
-                                                     const uint32_t *__restrict__ tot) {
+                                                     const uint32_t *__restrict__ tot,
+                                                     const Rec<T> *__restrict__ rec, double Lx,
+                                                     double Ly, typename Fix<T>::U *__restrict__ ux,
+                                                     typename Fix<T>::U *__restrict__ uy,
+                                                     T *__restrict__ zs, T *__restrict__ qs) {
     __shared__ BkLds<K> L;
     const int b = blockIdx.x, t = threadIdx.x, lane = t % WAVE, wave = t / WAVE;
     const int n = (int)tot[b];
-    if (n <= 1) return;
+    if (n == 0) return;
     // start = sum of tot[0 .. b - 1] (fixed order: wave sums, then the waves)
     uint32_t v = t < b ? tot[t] : 0u;
 #pragma unroll
@@ -417,10 +441,24 @@ __global__ __launch_bounds__(BK_THREADS) void k_bsort(K *__restrict__ keys,
     int64_t base = 0;
 #pragma unroll
     for (int w = 0; w < BK_WAVES; ++w) base += L.below[w];
+    // sorted position x of the bucket holds input particle o
+    auto gather = [&](int x, int32_t o) {
+        const Rec<T> r = rec[o];
+        const int64_t i = base + x;
+        ux[i] = Fix<T>::frac((double)r.x / Lx);
+        uy[i] = Fix<T>::frac((double)r.y / Ly);
+        zs[i] = r.z + (T)0;
+        qs[i] = r.q;
+    };
+    if (n == 1) {
+        if (t == 0) gather(0, vals[base]);
+        return;
+    }
     if (n > BkLds<K>::CAP) {
         // strongly clustered heights: in place in the work-group's own
         // global-memory region (visible to its threads across the barriers)
         bk_bitonic<K>(keys + base, vals + base, n);
+        for (int x = t; x < n; x += BK_THREADS) gather(x, vals[base + x]);
         return;
     }
     K lo = ~(K)0, hi = (K)0;
@@ -448,7 +486,11 @@ __global__ __launch_bounds__(BK_THREADS) void k_bsort(K *__restrict__ keys,
         kmax = max(kmax, L.kred[1][w]);
     }
     const K span = kmax - kmin;
-    if (span == 0) return;  // one key: the bucket is in input order already
+    if (span == 0) {
+        // one key: the bucket is in input order already
+        for (int x = t; x < n; x += BK_THREADS) gather(x, L.ia[x]);
+        return;
+    }
     const int bits = (int)(8 * sizeof(K)) -
                      (sizeof(K) == 4 ? __clz((uint32_t)span) : __clzll((unsigned long long)span));
     const int passes = (bits + 7) / 8;
@@ -466,25 +508,9 @@ __global__ __launch_bounds__(BK_THREADS) void k_bsort(K *__restrict__ keys,
     for (int x = t; x < n; x += BK_THREADS) {
         keys[base + x] = sk[x];
         vals[base + x] = si[x];
+        gather(x, si[x]);
     }
 }
-
-template <typename T>
-struct Fix;
-template <>
-struct Fix<float> {
-    using U = uint32_t;
-    __device__ static U frac(double v) {
-        // fixed-point fraction of a turn: round(frac(v) * 2^32) mod 2^32
-        double f = v - floor(v);
-        return (U)(uint64_t)llrint(f * 4294967296.0);
-    }
-};
-template <>
-struct Fix<double> {
-    using U = double;
-    __device__ static U frac(double v) { return v - floor(v); }
-};
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather(const Rec<T> *__restrict__ rec,
@@ -566,8 +592,11 @@ q2d_status sort_impl(Plan *p, const void *pos_v, const void *q_v, int64_t N) {
         k_scan_digit<<<256, 256, 0, p->stream>>>(hist, ntiles, tot);
         k_scatter<K, true><<<ntiles, SORT_THREADS, 0, p->stream>>>(kin, vin, kout, vout, N, 0,
                                                                   hist, tot, ntiles, scale);
-        k_bsort<K><<<BK_NB, BK_THREADS, 0, p->stream>>>(kout, vout, tot);
+        k_bsort<T, K><<<BK_NB, BK_THREADS, 0, p->stream>>>(
+            kout, vout, tot, (const Rec<T> *)p->recs.p, p->Lx, p->Ly, (U *)p->s_ux.p,
+            (U *)p->s_uy.p, (T *)p->s_z.p, (T *)p->s_q.p);
         p->perm = vout;
+        return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
     } else {
         const int passes = (int)sizeof(K);
         for (int pass = 0; pass < passes; ++pass) {
