@@ -289,6 +289,12 @@ __global__ void k_modes_out(const int32_t *modes, int P, int p_pad, int32_t *out
     }
 }
 
+// error bits of a sampler run into the plan's status word (which kernels on
+// the other stream may set at the same time)
+__global__ void k_word_or(int *dst, const int *src) {
+    if (*src) atomicOr(dst, *src);
+}
+
 // The two passes of the adjoint once the particles are sorted (and, for the
 // random batch, the modes drawn): sources q keep their field in p->fq, then
 // sources g give phi(g) and f(g), combined by the adjoint epilogue.
@@ -317,16 +323,31 @@ q2d_status vjp_passes(Plan *p, int64_t N, const int32_t *modes, const void *coef
 
 namespace q2d {
 
-q2d_status k0_side(Plan *p, int64_t N) {
+q2d_status ahead_hit_side(Plan *p, int P, int32_t *modes_out) {
+    k_word_or<<<1, 1, 0, p->stream>>>((int *)p->status.p, (const int *)p->sp_status.p);
+    if (modes_out) {
+        const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
+        k_modes_out<<<(P + 255) / 256, 256, 0, p->stream>>>((const int32_t *)p->rb_modes.p, P,
+                                                            p_pad, modes_out);
+    }
+    return hipGetLastError() == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
+}
+
+q2d_status k0_side(Plan *p, int64_t N, const SideExtra *ex) {
     if (hipEventRecord(p->ev_sorted, p->stream) != hipSuccess ||
         hipStreamWaitEvent(p->side, p->ev_sorted, 0) != hipSuccess)
         return Q2D_EDEVICE;
     q2d_status st = Q2D_OK;
     {
         SideScope side(p);
+        if (ex && ex->hit) st = ahead_hit_side(p, ex->P, ex->modes_out);
         // the epilogue's inverse permutation, off the critical path
-        if (!p->R && (st = launch_inv(p, N)) == Q2D_OK) p->inv_ready = true;
+        if (st == Q2D_OK && !p->R && (st = launch_inv(p, N)) == Q2D_OK) p->inv_ready = true;
         if (st == Q2D_OK) st = k0_run(p, N);
+        // the next step's modes: the main stream waits for ev_k0 before its
+        // epilogue, so they are in place before the next call's first launch
+        if (st == Q2D_OK && ex && ex->ahead)
+            st = sample_modes_ahead(p, ex->P, ex->seed, ex->next_step);
     }
     if (st != Q2D_OK) return st;
     return hipEventRecord(p->ev_k0, p->side) == hipSuccess ? Q2D_OK : Q2D_EDEVICE;
@@ -529,6 +550,7 @@ void plan_release(Plan *p) {
         p->pend_ev[w].clear();
     }
     Buf *bufs[] = {&p->exact_modes, &p->exact_coef, &p->rb_modes, &p->rb_coef, &p->rb_work,
+                   &p->sp_modes, &p->sp_coef, &p->sp_status,
                    &p->iid_tab,
                    &p->user_modes, &p->user_w, &p->user_coef, &p->s_g, &p->fq,
                    &p->keys_a, &p->keys_b, &p->vals_a, &p->vals_b, &p->hist, &p->s_ux,
@@ -598,6 +620,7 @@ q2d_status q2d_plan_destroy(q2d_plan_t p) {
 q2d_status q2d_plan_set_stream(q2d_plan_t p, void *stream) {
     if (!p) return Q2D_EINVAL;
     p->stream = (hipStream_t)stream;
+    p->spec_ok = false;
     return Q2D_OK;
 }
 
@@ -649,24 +672,53 @@ static q2d_status rbm_step_body(q2d_plan_t p, const void *pos, const void *q, in
                                 double *E, int32_t *modes_out) {
     q2d_status st;
     tstart(p, 4);
-    // the sampler runs on the side stream while the main stream sorts
     const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
-    if (hipEventRecord(p->ev_fork, p->stream) != hipSuccess ||
-        hipStreamWaitEvent(p->side, p->ev_fork, 0) != hipSuccess)
-        return Q2D_EDEVICE;
-    {
-        SideScope side(p);
-        if ((st = sample_modes(p, P, seed, step)) != Q2D_OK) return st;
-        if (modes_out)
-            k_modes_out<<<(P + 255) / 256, 256, 0, p->stream>>>((const int32_t *)p->rb_modes.p, P,
-                                                                p_pad, modes_out);
+    // Modes of this step sampled ahead by the previous call on this stream:
+    // the main stream waited for that call's ev_k0, which follows them.
+    SideExtra ex;
+    ex.P = P;
+    ex.modes_out = modes_out;
+    // not inside a stream capture: a graph would keep one step's buffer roles
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(p->stream, &cap) != hipSuccess) return Q2D_EDEVICE;
+    const bool plain = !p->arena && !p->serial && !p->R && cap == hipStreamCaptureStatusNone;
+    ex.hit = plain && N > 0 && p->spec_ok && p->spec_seed == seed && p->spec_step == step &&
+             p->spec_P == P && p->spec_stream == p->stream;
+    ex.ahead = plain && N > 0;
+    ex.seed = seed;
+    ex.next_step = step + 1;
+    if (ex.hit) {
+        std::swap(p->rb_modes, p->sp_modes);
+        std::swap(p->rb_coef, p->sp_coef);
     }
-    if (hipEventRecord(p->ev_modes, p->side) != hipSuccess) return Q2D_EDEVICE;
+    if (plain) p->spec_ok = false;
+    if (!ex.hit) {
+        // the sampler runs on the side stream while the main stream sorts
+        if (hipEventRecord(p->ev_fork, p->stream) != hipSuccess ||
+            hipStreamWaitEvent(p->side, p->ev_fork, 0) != hipSuccess)
+            return Q2D_EDEVICE;
+        {
+            SideScope side(p);
+            if ((st = sample_modes(p, P, seed, step)) != Q2D_OK) return st;
+            if (modes_out)
+                k_modes_out<<<(P + 255) / 256, 256, 0, p->stream>>>(
+                    (const int32_t *)p->rb_modes.p, P, p_pad, modes_out);
+        }
+        if (hipEventRecord(p->ev_modes, p->side) != hipSuccess) return Q2D_EDEVICE;
+    }
     int nch = 0;
     if (N > 0) {
         if ((st = sort_and_stage(p, pos, q, N)) != Q2D_OK) return st;
-        if ((st = k0_side(p, N)) != Q2D_OK) return st;
-        if (hipStreamWaitEvent(p->stream, p->ev_modes, 0) != hipSuccess) return Q2D_EDEVICE;
+        if ((st = k0_side(p, N, &ex)) != Q2D_OK) return st;
+        if (ex.ahead) {
+            p->spec_ok = true;
+            p->spec_seed = seed;
+            p->spec_step = step + 1;
+            p->spec_P = P;
+            p->spec_stream = p->stream;
+        }
+        if (!ex.hit && hipStreamWaitEvent(p->stream, p->ev_modes, 0) != hipSuccess)
+            return Q2D_EDEVICE;
         if ((st = kmodes_run(p, N, (const int32_t *)p->rb_modes.p, p->rb_coef.p, p_pad, 0, P,
                              &nch)) != Q2D_OK)
             return st;

@@ -177,6 +177,14 @@ struct Plan {
     Buf spans;                 // FP64 complex W,G per (segment, pair)
     Buf agg;                   // aggregates / carries (both directions)
     Buf carry_tmp;             // per-range transfers of the carry scan
+    // the next random-batch step's modes, sampled ahead on the internal stream
+    // at the end of a q2d_rbm_step call; the next call swaps them in when it
+    // asks for (spec_seed, spec_step, spec_P) on the same stream
+    Buf sp_modes, sp_coef, sp_status;
+    bool spec_ok = false;
+    uint64_t spec_seed = 0, spec_step = 0;
+    int32_t spec_P = 0;
+    hipStream_t spec_stream = nullptr;
     Buf outk;                  // per-chunk per-particle outputs (T x 4)
 
     // k = 0 scans (own carry scratch: they run concurrently with the k != 0 scans)
@@ -290,7 +298,7 @@ q2d_status build_mode_coefs(Plan *p, const int32_t *modes, int64_t n, int64_t n_
 // cumulative tables of the i.i.d. mode sampler (host)
 void iid_tables(double alpha, double Lx, double Ly, std::vector<double> &tab, int *mxm, int *mym);
 // random-batch sampler: writes p->rb_modes and p->rb_coef for P modes
-q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step);
+q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step, int *status = nullptr);
 // replica batches: P modes per replica ([r][2][p_pad], [r][fields][p_pad]);
 // step is read from step_dev when it is not null (captured steps)
 q2d_status sample_modes_batch(Plan *p, int P, uint64_t seed, uint64_t step,
@@ -332,9 +340,25 @@ struct SideScope {
     ~SideScope() { p->stream = saved; }
 };
 
+// Extra work of a random-batch step on the internal stream: with modes
+// sampled ahead (hit), their sampler status and the caller's mode copy; and
+// the next step's modes sampled ahead after the k = 0 term (ahead).
+struct SideExtra {
+    bool hit = false;
+    int32_t *modes_out = nullptr;
+    int P = 0;
+    bool ahead = false;
+    uint64_t seed = 0, next_step = 0;
+};
+
 // the k = 0 term on the internal stream once the sorted data exist; the main
 // stream must wait for ev_k0 before reading phi0 / fz0
-q2d_status k0_side(Plan *p, int64_t N);
+q2d_status k0_side(Plan *p, int64_t N, const SideExtra *ex = nullptr);
+// the modes of (seed, step) into sp_modes / sp_coef, sampler status into sp_status
+q2d_status sample_modes_ahead(Plan *p, int P, uint64_t seed, uint64_t step);
+// on p->stream: the sampled-ahead status bits into the plan's status word, and
+// the modes of rb_modes into the caller's array
+q2d_status ahead_hit_side(Plan *p, int P, int32_t *modes_out);
 
 // short range
 q2d_status short_range_run(Plan *p, const void *pos, const void *q, int64_t N, void *phi, void *F,

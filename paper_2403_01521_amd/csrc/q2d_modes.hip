@@ -326,7 +326,7 @@ void sampler_reqs(Plan *p, int P, Reqs &q) {
     q.add(p->rb_coef, (size_t)coef_fields(p->mh) * p_pad * tsz);
 }
 
-q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step) {
+q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step, int *status) {
     const double PI = 3.14159265358979323846;
     Reqs req;
     sampler_reqs(p, P, req);
@@ -348,11 +348,28 @@ q2d_status sample_modes(Plan *p, int P, uint64_t seed, uint64_t step) {
     double *wgt = (double *)((char *)p->rb_work.p + (size_t)n * 2 * sizeof(int32_t));
     double *uacc = wgt + n;
     k_sample<<<1, 1024, 0, p->stream>>>(P, D, seed, step, p->alpha, p->Lx, p->Ly, prop, wgt, uacc,
-                                         (int32_t *)p->rb_modes.p, p_pad, (int *)p->status.p,
-                                         nullptr, nullptr);
+                                         (int32_t *)p->rb_modes.p, p_pad,
+                                         status ? status : (int *)p->status.p, nullptr, nullptr);
     if (hipGetLastError() != hipSuccess) return Q2D_EDEVICE;
     return build_mode_coefs(p, (const int32_t *)p->rb_modes.p, P, p_pad, nullptr,
                             PI / (p->Lx * p->Ly) * p->H / P, p->rb_coef.p);
+}
+
+__global__ void k_word_zero(int *a) { *a = 0; }
+
+// The next step's modes, sampled ahead into the second buffers (swapped with
+// rb_modes / rb_coef around the sampler, which also fills them), with its own
+// status word: a step never asked for must not raise the plan's status.
+q2d_status sample_modes_ahead(Plan *p, int P, uint64_t seed, uint64_t step) {
+    q2d_status st;
+    if ((st = ensure(p, p->sp_status, sizeof(int))) != Q2D_OK) return st;
+    k_word_zero<<<1, 1, 0, p->stream>>>((int *)p->sp_status.p);
+    std::swap(p->rb_modes, p->sp_modes);
+    std::swap(p->rb_coef, p->sp_coef);
+    st = sample_modes(p, P, seed, step, (int *)p->sp_status.p);
+    std::swap(p->rb_modes, p->sp_modes);
+    std::swap(p->rb_coef, p->sp_coef);
+    return st;
 }
 
 q2d_status sample_modes_batch(Plan *p, int P, uint64_t seed, uint64_t step,

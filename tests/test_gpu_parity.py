@@ -229,6 +229,50 @@ def test_sort_paths_agree(soe_tables, prec, monkeypatch):
     plan.close()
 
 
+@pytest.mark.parametrize("sampler", ["metropolis", "iid"])
+def test_modes_sampled_ahead(soe_tables, sampler):
+    """A random-batch step samples the next step's modes on the internal
+    stream; the next call on the same stream with (seed, step + 1, P) uses
+    them.  Every such call, and every call that cannot use them (another step,
+    another P, another stream, the allocation-free entry point in between),
+    gives bitwise what a fresh plan gives for that (seed, step, P)."""
+    c = wl.make_config(3, dtype=np.float32, n_override=30000)
+    w, s = soe_tables[16]
+    gp, gq = dev(c["pos"], torch.float32), dev(c["q"], torch.float32)
+
+    def make():
+        return q2d.Plan(c["box"], c["alpha"], w, s, precision="fp32", n_max=len(c["q"]),
+                        p_max=96, sampler=sampler)
+
+    def fresh(P, step):
+        f = make()
+        out = [x.clone() for x in f.rbm_step(gp, gq, P, seed=11, step=step)]
+        f.close()
+        return out
+
+    plan = make()
+    other = torch.cuda.Stream()
+    calls = [(64, 5), (64, 6), (64, 7), (64, 9), (96, 10), (64, 11), (64, 12), ("noalloc", 13),
+             (64, 13), ("stream", 14), (64, 15)]
+    for P, step in calls:
+        if P == "noalloc":
+            got = [x.clone() for x in plan.rbm_step_noalloc(gp, gq, 64, seed=11, step=step)]
+            P = 64
+        elif P == "stream":
+            P = 64
+            other.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(other):
+                got = [x.clone() for x in plan.rbm_step(gp, gq, P, seed=11, step=step)]
+            torch.cuda.current_stream().wait_stream(other)
+        else:
+            got = [x.clone() for x in plan.rbm_step(gp, gq, P, seed=11, step=step)]
+        ref = fresh(P, step)
+        for x, y in zip(got, ref):
+            assert torch.equal(x, y), (P, step)
+    assert plan.check() == 0
+    plan.close()
+
+
 def test_equal_heights_square_lattice(soe_tables):
     """All ions in one plane (sort ties): the square ionic lattice."""
     w, s = soe_tables[24]
