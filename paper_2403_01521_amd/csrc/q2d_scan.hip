@@ -389,7 +389,8 @@ struct SpanArgs {
 // powers u^n are mode-independent columns of the contraction (8 per
 // direction, in one extra column tile); each mode combines its 8 sums with
 // its own coefficients afterwards.  Segments whose span is too wide for the
-// largest |k| of the launch keep the per-particle exponentials on the VALU.
+// largest |k| of the launch, and tables of more than 16 terms (whose pairs
+// already take three tiles), keep the per-particle exponentials on the VALU.
 constexpr int KT_DEG = 7;
 constexpr float KT_MAX = 0.4f;
 
@@ -483,7 +484,10 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
 #pragma unroll
             for (int cc = 0; cc < CPW; ++cc) fk[cc][0] = fk[cc][1] = fk[cc][2] = fk[cc][3] = 0.f;
             // this lane's particle of the next block, loaded a block ahead so
-            // that the loads complete during the contraction
+            // that the loads complete during the contraction (tables of at
+            // most 16 terms: with more, the registers held across the
+            // contraction would lower the occupancy)
+            constexpr bool PREF = NCT <= 2;
             float nz = 0.f, nq = 0.f;
             uint32_t nux = 0, nuy = 0;
             auto fetch = [&](int blk) {
@@ -500,13 +504,14 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
                     }
                 }
             };
-            fetch(0);
+            if (PREF) fetch(0);
             // every load so far done here (vmcnt(0)): a mode's table entries
             // would otherwise be waited for inside the block loop, whose wait
             // then also takes in the loads of the next block
-            __builtin_amdgcn_s_waitcnt(0x0F70);
+            if (PREF) __builtin_amdgcn_s_waitcnt(0x0F70);
             for (int blk = 0; blk < nblk; ++blk) {
                 __syncthreads();
+                if (!PREF) fetch(blk);
                 {
                     // particle lane of the block; wave wv stages pairs wv, wv + AGW, ...
                     const int pos = blk * WAVE + lane;
@@ -556,7 +561,7 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
                     }
                     // after the staging: its own loads (the pair exponents)
                     // wait for every load in flight
-                    if (blk + 1 < nblk) fetch(blk + 1);
+                    if (PREF && blk + 1 < nblk) fetch(blk + 1);
                 }
                 __syncthreads();
                 if (!act) continue;
@@ -683,10 +688,16 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
             }
         }
     };
-    if (km * span <= KT_MAX)
-        passes(std::true_type{});
-    else
+    // the extra column tile only while the contraction has at most two (more
+    // would lower the occupancy of the whole kernel)
+    if constexpr (NCT <= 2) {
+        if (km * span <= KT_MAX)
+            passes(std::true_type{});
+        else
+            passes(std::false_type{});
+    } else {
         passes(std::false_type{});
+    }
 }
 
 // ---------------------------------------------------------------------------
