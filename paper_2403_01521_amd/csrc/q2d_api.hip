@@ -665,6 +665,22 @@ q2d_status q2d_long_range(q2d_plan_t p, const void *pos, const void *q, int64_t 
     return st;
 }
 
+// Whether work enqueued on the plan's stream now goes into a graph (a failed
+// query counts as yes).  From the first such call on, the plan samples no
+// modes ahead: a replay of the captured sampler writes the plan's mode
+// buffers, one of which may hold modes sampled ahead for an eager call.
+static bool capture_guard(Plan *p) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(p->stream, &cap) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = hipStreamCaptureStatusActive;
+    }
+    if (cap == hipStreamCaptureStatusNone) return false;
+    p->no_ahead = true;
+    p->spec_ok = false;
+    return true;
+}
+
 // The random-batch step after the argument checks (shared by q2d_rbm_step and
 // its allocation-free variant).
 static q2d_status rbm_step_body(q2d_plan_t p, const void *pos, const void *q, int64_t N,
@@ -678,10 +694,7 @@ static q2d_status rbm_step_body(q2d_plan_t p, const void *pos, const void *q, in
     SideExtra ex;
     ex.P = P;
     ex.modes_out = modes_out;
-    // not inside a stream capture: a graph would keep one step's buffer roles
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(p->stream, &cap) != hipSuccess) return Q2D_EDEVICE;
-    const bool plain = !p->arena && !p->serial && !p->R && cap == hipStreamCaptureStatusNone;
+    const bool plain = !p->arena && !p->serial && !p->R && !capture_guard(p) && !p->no_ahead;
     ex.hit = plain && N > 0 && p->spec_ok && p->spec_seed == seed && p->spec_step == step &&
              p->spec_P == P && p->spec_stream == p->stream;
     ex.ahead = plain && N > 0;
@@ -815,6 +828,7 @@ q2d_status q2d_rbm_step_vjp(q2d_plan_t p, const void *pos, const void *q, const 
     if (p->opts.p_max <= 0) return Q2D_EUNSUPPORTED;
     if (P > p->opts.p_max) return Q2D_ECAPACITY;
     if (N == 0) return Q2D_OK;
+    (void)capture_guard(p);
     tstart(p, 4);
     const int p_pad = ((P + WAVE - 1) / WAVE) * WAVE;
     if (hipEventRecord(p->ev_fork, p->stream) != hipSuccess ||

@@ -182,6 +182,7 @@ struct Plan {
     // asks for (spec_seed, spec_step, spec_P) on the same stream
     Buf sp_modes, sp_coef, sp_status;
     bool spec_ok = false;
+    bool no_ahead = false;  // set once a step of this plan was captured into a graph
     uint64_t spec_seed = 0, spec_step = 0;
     int32_t spec_P = 0;
     hipStream_t spec_stream = nullptr;

@@ -273,6 +273,60 @@ def test_modes_sampled_ahead(soe_tables, sampler):
     plan.close()
 
 
+@pytest.mark.parametrize("entry", ["rbm_step", "rbm_step_noalloc"])
+def test_step_captured_by_caller(soe_tables, entry):
+    """A caller captures one random-batch step into a graph (scratch already
+    allocated by an eager call): every replay, with eager steps of other draws
+    and synchronisations in between, gives bitwise the eager result of the
+    captured (seed, step), and the eager steps around the replays (consecutive
+    draws, which would use modes sampled ahead) give bitwise what a fresh plan
+    gives: a replay rewrites the plan's mode buffers."""
+    c = wl.make_config(3, dtype=np.float32, n_override=20000)
+    w, s = soe_tables[16]
+    gp, gq = dev(c["pos"], torch.float32), dev(c["q"], torch.float32)
+    P = 64
+    plan = q2d.Plan(c["box"], c["alpha"], w, s, precision="fp32", n_max=len(c["q"]), p_max=P)
+    step = getattr(plan, entry)
+    ref = [x.clone() for x in plan.rbm_step(gp, gq, P, seed=21, step=7)]
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        step(gp, gq, P, seed=21, step=6)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cs):
+        out = step(gp, gq, P, seed=21, step=7)
+    torch.cuda.synchronize()
+    def fresh(st):
+        f = q2d.Plan(c["box"], c["alpha"], w, s, precision="fp32", n_max=len(c["q"]), p_max=P)
+        o = [x.clone() for x in f.rbm_step(gp, gq, P, seed=21, step=st)]
+        f.close()
+        return o
+
+    def eager(st):
+        got = [x.clone() for x in plan.rbm_step(gp, gq, P, seed=21, step=st)]
+        for x, y in zip(got, fresh(st)):
+            assert torch.equal(x, y), (entry, st)
+
+    # consecutive eager steps with replays between them (steps 8, 9, replay,
+    # 10, 11, replay, ...): with modes sampled ahead, one of the replays would
+    # land on the buffer that holds the next step's modes
+    st = 8
+    for r in range(3):
+        eager(st)
+        eager(st + 1)
+        g.replay()
+        torch.cuda.synchronize()
+        for x, y in zip(out, ref):
+            assert torch.equal(x, y), (entry, r)
+        st += 2
+    eager(st)
+    assert plan.check() == 0
+    del g
+    plan.close()
+
+
 def test_equal_heights_square_lattice(soe_tables):
     """All ions in one plane (sort ties): the square ionic lattice."""
     w, s = soe_tables[24]
