@@ -141,6 +141,11 @@ q2d_status q2d_long_range(q2d_plan_t plan, const void *pos, const void *q, int64
  * phi_self, with forces and E as in q2d_long_range.  modes_out: device int32
  * array of P x 2 (mx, my) with k = 2 pi (mx/Lx, my/Ly), or NULL.
  * Q2D_ECAPACITY if P > p_max.
+ * Each call also draws the modes of (seed, step + 1, P) on the plan's internal
+ * stream; a following call with exactly those arguments on the same stream
+ * uses them (same results, less waiting).  A plan on which a random-batch
+ * step or its adjoint was ever called inside a stream capture stops drawing
+ * ahead (replays of the capture rewrite the plan's mode buffers).
  */
 q2d_status q2d_rbm_step(q2d_plan_t plan, const void *pos, const void *q, int64_t N, int32_t P,
                         uint64_t seed, uint64_t step, void *phi, void *F, double *E,
