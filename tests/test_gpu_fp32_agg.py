@@ -14,7 +14,9 @@ path (which does not use fp16):
   FP64 O(N) recursion of the oracle (O3) on the same modes within 2e-5, per
   particle as well as in norm; for mixed magnitudes also over the unit
   charges alone (whose sources sit near the fp16 normal range after the
-  per-segment scaling, and whose forces the +-1000 ions dominate in the norm).
+  per-segment scaling, and whose forces the +-1000 ions dominate in the norm);
+* the Taylor columns of the beta = k term: segments on both sides of the
+  |k|max x span <= 0.4 threshold in one launch, against O3 segment by segment.
 """
 import numpy as np
 import pytest
@@ -132,3 +134,59 @@ def test_fp32_vs_fp64_hard_inputs(soe_tables, maker):
                                                         prel(F32[unit], F64[unit])))
         assert_close(phi32[unit], phi64[unit], 2e-5, "phi |q|=1")
         assert_close(F32[unit], F64[unit], 2e-5, "F |q|=1")
+
+
+def test_taylor_columns_threshold(soe_tables):
+    """The beta = k aggregate of a segment goes through Taylor columns in
+    u = t / Delta when (largest |k| of the launch) x (segment span Delta) is at
+    most 0.4, and through per-particle exponentials otherwise.  Eight segments
+    of 512 particles with spans 0.05 ... 6 in units of 1 / |k|max (0.39 and
+    0.41 on either side of the threshold) in one launch of a fixed mode list
+    whose largest |k| is 1: FP32 against the FP64 O(N) recursion (O3), per
+    particle and in norm, and segment by segment."""
+    box = (20 * np.pi, 20 * np.pi, 40.0)  # k = (mx, my) / 10
+    alpha = 0.5
+    w, s = soe_tables[16]
+    rng = np.random.default_rng(1234)
+    spans = [0.05, 0.2, 0.39, 0.41, 0.6, 1.5, 3.0, 6.0]
+    S = 512
+    zs, z0 = [], 1.0
+    for d in spans:
+        z = z0 + d * rng.uniform(0.0, 1.0, S)
+        z[0], z[-1] = z0, z0 + d  # the segment's span is exactly d
+        zs.append(np.sort(z))
+        z0 += d + 1.0
+    assert z0 < box[2]
+    z = np.concatenate(zs)
+    n = len(z)
+    pos = np.stack([rng.uniform(0, box[0], n), rng.uniform(0, box[1], n), z], axis=1)
+    q = rng.permutation(np.repeat([1.0, -1.0], n // 2))  # neutral
+    pos32, q32 = pos.astype(np.float32), q.astype(np.float32)
+    modes = np.array([[10, 0]] + [list(m) for m in rng.integers(-7, 8, size=(95, 2))
+                                  if (m[0], m[1]) != (0, 0)])
+    kmag = np.hypot(modes[:, 0], modes[:, 1]) / 10.0
+    assert kmag.max() == 1.0
+    wt = rng.uniform(0.5, 2.0, len(modes)) * np.pi / (box[0] * box[1])
+    plan = q2d.Plan(box, alpha, w, s, precision="fp32", n_max=n)
+    phi, F, E = plan.modes_eval(dev(pos32, torch.float32), dev(q32, torch.float32),
+                                dev(modes.astype(np.int32), torch.int32),
+                                dev(wt, torch.float64))
+    torch.cuda.synchronize()
+    phi, F = phi.double().cpu().numpy(), F.double().cpu().numpy()
+    plan.close()
+    p64, q64 = pos32.astype(np.float64), q32.astype(np.float64)
+    r = o3.long_range(p64, q64, box, alpha, w, s, modes, wt, include_self_pair=False, diag=0.0,
+                      nthreads=8)
+    r0 = o3.long_range(p64, q64, box, alpha, w, s, np.zeros((0, 2), int), np.zeros(0),
+                       include_self_pair=False, diag=0.0, nthreads=1)
+    ref_phi, ref_F = r["phi"] - r0["phi"], r["F"] - r0["F"]
+    print("taylor threshold: phi %.2e F %.2e" % (rel(phi, ref_phi), rel(F, ref_F)))
+    assert_close(phi, ref_phi, 2e-5, "phi")
+    assert_close(F, ref_F, 2e-5, "F")
+    # the sorted order is the input order here: segment g is rows g S .. (g + 1) S
+    scale = np.sqrt(np.mean(np.sum(ref_F**2, axis=1)))
+    for g, d in enumerate(spans):
+        sl = slice(g * S, (g + 1) * S)
+        err = np.abs(F[sl] - ref_F[sl]).max() / scale
+        print("  span %.2f: max |dF| / rms F = %.2e" % (d, err))
+        assert err < 5e-5, (d, err)
