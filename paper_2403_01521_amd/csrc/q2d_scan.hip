@@ -606,7 +606,12 @@ __global__ __launch_bounds__(AGW_MAX * WAVE) void k_agg_seg(const KArgs<float> a
                             ay = __builtin_amdgcn_mfma_f32_16x16x32_f16(yh, bl[c], ay, 0, 0, 0);
                             ay = __builtin_amdgcn_mfma_f32_16x16x32_f16(yl, bh[c], ay, 0, 0, 0);
                         }
-                        __builtin_amdgcn_sched_barrier(0);
+                        // one chunk's work at a time (interleaving the next
+                        // chunk's VALU work with these matrix instructions
+                        // needs 170+ VGPRs, 2 waves per SIMD); only LDS reads
+                        // (mask 0x100) may move across, so the next chunk's
+                        // particle data is read while these run
+                        __builtin_amdgcn_sched_barrier(0x0100);
                     }
                 }
             }
